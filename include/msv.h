@@ -1,0 +1,241 @@
+/*
+ * msv.h - C ABI of the compressed state-vector simulator for AMD MI355X (gfx950).
+ *
+ * The method (MEMQSim, Sec. 2 "Design and Preliminary Result"): the state
+ * vector of 2^n complex amplitudes is partitioned into chunks that are each
+ * compressed independently ("Offline stage"); the circuit is partitioned into
+ * stages, and each stage runs as one pass that loads chunks, decompresses
+ * them, updates the amplitudes on the GPU, recompresses and stores them back
+ * ("Online stage", steps (1)-(6)), until every amplitude has been updated,
+ * then the next stage starts. Here the whole decompress -> apply -> recompress
+ * pass runs in HIP kernels on one GPU; the compressed chunks live in HBM or in
+ * pinned host memory.
+ *
+ * Conventions
+ *   - Every function returns an int status: MSV_OK (0) or a negative MSV_E_*.
+ *     No function aborts or throws. msv_last_error() gives the message.
+ *   - Argument errors (MSV_E_ARG, MSV_E_RANGE on inputs) leave the handle
+ *     usable. MSV_E_DEVICE (a HIP runtime error) poisons the handle: later
+ *     calls on it return MSV_E_STATE until msv_destroy().
+ *   - One thread at a time per handle. Handles are independent.
+ *   - Qubits are little-endian: amplitude index i = sum_q b_q 2^q. A two-qubit
+ *     gate on (q0, q1) indexes its 4x4 matrix by s = b(q0) + 2 b(q1).
+ *   - Complex buffers are interleaved (re, im): double for MSV_C128, float for
+ *     MSV_C64. Host buffers are caller-owned; the library copies from them
+ *     during the call and keeps no pointer after it returns.
+ */
+#ifndef MSV_C_ABI_H_
+#define MSV_C_ABI_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+enum {
+    MSV_OK = 0,
+    MSV_E_ARG = -1,         /* invalid argument; nothing changed           */
+    MSV_E_NOMEM = -2,       /* host or device allocation failed            */
+    MSV_E_DEVICE = -3,      /* HIP runtime error; the handle is poisoned   */
+    MSV_E_RANGE = -4,       /* non-finite value, or a code beyond 2^30-1   */
+    MSV_E_STATE = -5,       /* wrong call order, or poisoned handle        */
+    MSV_E_CORRUPT = -6,     /* a compressed chunk failed validation        */
+    MSV_E_UNSUPPORTED = -7, /* valid request outside what is implemented   */
+    MSV_E_NORM = -8         /* normalisation of a zero-norm state          */
+};
+
+enum msv_dtype { MSV_C128 = 0, MSV_C64 = 1 };
+enum msv_store { MSV_STORE_DEVICE = 0, MSV_STORE_HOST_PINNED = 1 };
+/* Arithmetic of fused dense gates: FP64 (complex128 states), FP32 or BF16
+ * matrix-core inputs with FP32 accumulation (complex64 states). */
+enum msv_mma { MSV_MMA_F64 = 0, MSV_MMA_F32 = 1, MSV_MMA_BF16 = 2 };
+
+/* Gate kinds. Matrices (theta = angle):
+ *   H, X, Y = [[0,-i],[i,0]], Z, S = diag(1,i), T = diag(1,e^{i pi/4}),
+ *   RX/RY/RZ(theta) = exp(-i theta P/2) for P = X/Y/Z, P(theta) = diag(1,e^{i theta}),
+ *   CX (control q0, target q1), CZ, CP(theta) = diag(1,1,1,e^{i theta}), SWAP,
+ *   U1 = caller 2x2, U2 = caller 4x4 (row-major, interleaved re/im, FP64). */
+enum msv_kind {
+    MSV_H = 0, MSV_X, MSV_Y, MSV_Z, MSV_S, MSV_T, MSV_RX, MSV_RY, MSV_RZ, MSV_P,
+    MSV_CX, MSV_CZ, MSV_CP, MSV_SWAP, MSV_U1, MSV_U2
+};
+
+typedef struct msv_gate {
+    uint32_t kind;      /* enum msv_kind                                      */
+    int32_t q0, q1;     /* q1 = -1 for one-qubit gates                        */
+    double theta;       /* angle of RX/RY/RZ/P/CP                             */
+    int32_t param;      /* adjoint: parameter index feeding theta, -1 = fixed */
+    const double *mat;  /* U1/U2 only; copied during the call                 */
+} msv_gate;
+
+/* Statistics of the last msv_apply (and running totals where noted). */
+typedef struct msv_stats {
+    uint64_t passes;             /* streamed passes (stages) of the last apply    */
+    uint64_t gates;              /* input gates of the last apply                 */
+    uint64_t fused_ops;          /* kernel-level ops after fusion                 */
+    uint64_t h2d_bytes;          /* host->device bytes of the last apply          */
+    uint64_t d2h_bytes;          /* device->host bytes of the last apply          */
+    uint64_t compressed_bytes;   /* current compressed state size (codes+meta)   */
+    uint64_t uncompressed_bytes; /* 2^n * sizeof(complex)                         */
+    uint64_t reserved_bytes;     /* memory reserved for the state store           */
+    double ratio;                /* uncompressed_bytes / compressed_bytes         */
+    double max_err_last;         /* max |x - x'| of the last pass (FP64)          */
+    double max_err_all;          /* max |x - x'| over every pass since init       */
+    double err_bound;            /* allowed |x - x'|: eb (1 + 2^-20) + rounding   */
+    double norm2;                /* sum |psi|^2 before the last encode (FP64)     */
+    double t_total;              /* seconds, wall time of the last apply          */
+    double t_h2d, t_d2h;         /* seconds of copies (host store)                */
+    double t_kernel;             /* seconds of kernels (events)                   */
+    double overlap;              /* fraction of copy time hidden under kernels    */
+    uint64_t bound_violations;   /* passes whose max error exceeded err_bound     */
+    uint64_t kernel_launches;    /* kernels launched by the last apply            */
+} msv_stats;
+
+typedef struct msv_sim msv_sim;  /* opaque, library-owned */
+
+/* ---- lifetime ------------------------------------------------------------ */
+
+/* Create a simulator for n_qubits (6..40) of dtype MSV_C128 or MSV_C64.
+ * Defaults: chunk = 2^min(n, 20) amplitudes, eb = 0 (uncompressed, state held
+ * as plain amplitudes in HBM), store = device, fusion k_max = 2. No device
+ * memory is touched until msv_init_*. */
+int msv_create(int n_qubits, int dtype, msv_sim **out);
+void msv_destroy(msv_sim *sim);
+
+/* Thread-local message of the last failing call (sim may be NULL for calls
+ * without a handle). Never NULL. */
+const char *msv_last_error(const msv_sim *sim);
+
+/* ---- configuration (before msv_init_*) ------------------------------------ */
+
+/* Chunk = 2^log2_chunk amplitudes, 6 <= log2_chunk <= n. Chunks are the unit of
+ * independent compression (Sec. 2, "Offline stage"). */
+int msv_set_chunk_qubits(msv_sim *sim, int log2_chunk);
+/* Absolute error bound per real/imag component. 0 = uncompressed. eb > 0 turns
+ * on the codec: codes q = rint(x / (2 eb)), |q| <= 2^30 - 1. */
+int msv_set_error_bound(msv_sim *sim, double eb);
+/* MSV_STORE_DEVICE (compressed chunks in HBM) or MSV_STORE_HOST_PINNED
+ * (compressed chunks in pinned host memory, streamed per pass). */
+int msv_set_store(msv_sim *sim, int store);
+/* Fuse consecutive gates into dense unitaries of at most k_max (1..5) qubits;
+ * mma_precision selects the arithmetic of fused ops (enum msv_mma). */
+int msv_set_fusion(msv_sim *sim, int k_max, int mma_precision);
+/* Named numeric options:
+ *   "tile_qubits"  log2 amplitudes per workgroup tile (6..13; 0 = automatic)
+ *   "renormalize"  1 = rescale to unit norm at the next decode after each pass
+ *   "check_bound"  1 (default) = FP64 max |x - x'| per pass
+ *   "mfma_min_k"   smallest fused width run on matrix cores (3..6; 6 = never)
+ *   "batch_chunks" host store: chunks per streamed batch (0 = automatic) */
+int msv_set_option(msv_sim *sim, const char *key, double value);
+/* Device memory provider (e.g. a framework's caching allocator). alloc returns
+ * NULL on failure; both are called on the calling thread. Without it the
+ * library uses hipMalloc/hipFree. */
+int msv_set_device_allocator(msv_sim *sim, void *(*alloc)(size_t, void *),
+                             void (*dealloc)(void *, void *), void *ctx);
+/* Stream (hipStream_t) on which every kernel and copy of this handle is
+ * queued. NULL = the library's own stream. */
+int msv_set_stream(msv_sim *sim, void *hip_stream);
+
+/* ---- state ------------------------------------------------------------------ */
+
+/* psi = |index>. Written directly in compressed form (all-zero chunks are
+ * header-only); the full state is never materialised. */
+int msv_init_basis(msv_sim *sim, uint64_t index);
+/* psi = host amplitudes (2^n complex of the handle's dtype), compressed on the
+ * GPU when eb > 0. For tests and for importing states. */
+int msv_init_state(msv_sim *sim, const void *host_amps);
+
+/* Apply gates in list order (Sec. 2, "Online stage"): the list is partitioned
+ * into passes; each pass streams every chunk through decode -> fused gates ->
+ * encode on the GPU. Blocks until the pass results and statistics are final.
+ * Returns MSV_E_RANGE if a value left the codec range (the state is then
+ * undefined and must be re-initialised). */
+int msv_apply(msv_sim *sim, const msv_gate *gates, size_t n_gates);
+
+/* ---- measurement (FP64 reductions on the GPU) ------------------------------ */
+
+/* P(qubit = 1) = sum over i with bit q set of |psi_i|^2. */
+int msv_prob_one(msv_sim *sim, int qubit, double *p1);
+/* out = sum_k coeffs[k] <psi| Z(z_masks[k]) |psi>, Z(m) = product of Z over the
+ * set bits of m: sum_i |psi_i|^2 sum_k c_k (-1)^popcount(i & m_k). */
+int msv_expect_z(msv_sim *sim, const uint64_t *z_masks, const double *coeffs,
+                 size_t n_terms, double *out);
+/* Copy amplitudes [first, first+count) (decoded) to host_out in the handle's
+ * dtype. */
+int msv_get_amplitudes(msv_sim *sim, uint64_t first, uint64_t count, void *host_out);
+/* Overlap with a caller state ref (2^n complex128, host): f_raw =
+ * |<ref|psi>|^2, f_norm = f_raw / (<psi|psi> <ref|ref>). MSV_E_NORM if a norm
+ * is zero (f_raw is still written). */
+int msv_fidelity(msv_sim *sim, const double *ref_c128, double *f_raw, double *f_norm);
+int msv_get_stats(msv_sim *sim, msv_stats *out);
+/* Canonical compressed bytes of one chunk (format "MSVC" v1, as produced by
+ * msv_codec_encode). *out_bytes receives the size; cap may be 0 to query. */
+int msv_export_chunk(msv_sim *sim, uint64_t chunk, void *host_out, size_t cap,
+                     size_t *out_bytes);
+
+/* ---- codec on its own ---------------------------------------------------------
+ * Format "MSVC" v1 for a chunk of C = 2^log2_chunk complex values:
+ *   32-byte header: u32 magic 0x4356534D, u8 version 1, u8 kind (0 ZERO,
+ *   1 GENERAL), u8 log2C, u8 dtype, f64 eb, u64 total_bytes, u32 n_blocks
+ *   (= 2C/64), u32 0. GENERAL chunks continue with u8 W[n_blocks] and
+ *   i32 A[n_blocks] (each zero-padded to 8 bytes) and the payload: for stream
+ *   block b = 2j + p (j = 64-amplitude block, p = 0 real / 1 imaginary) W[b]
+ *   64-bit words whose bit i is bit k of zigzag(q_i - q_(i-1)) (d_0 = 0),
+ *   A[b] = q_0. Runs on the GPU. */
+int msv_codec_encode(int dtype, int log2_chunk, double eb, const void *host_in,
+                     void *host_out, size_t cap, size_t *out_bytes);
+/* Decode one chunk into host_out (2^log2C complex of the header's dtype).
+ * MSV_E_CORRUPT on a malformed chunk. */
+int msv_codec_decode(int dtype, const void *host_in, size_t in_bytes, void *host_out);
+/* Worst-case encoded size of one chunk. */
+size_t msv_codec_bound(int log2_chunk);
+
+/* ---- adjoint differentiation ------------------------------------------------- */
+
+/* Expectation of sum_k c_k Z(m_k) after the parameterised circuit and its
+ * gradient with respect to params (gates with param >= 0 take theta =
+ * params[param]; only RX, RY, RZ, P and CP may be parameterised, each
+ * parameter feeding gates of one kind). Forward pass with compressed
+ * checkpoints before gate indices ckpt_at[0..n_ckpt), then a reverse sweep
+ * that recomputes each segment from its checkpoint and applies U^dagger to the
+ * state and to lambda = O psi. grad has n_params entries. */
+int msv_adjoint(msv_sim *sim, const msv_gate *gates, size_t n_gates,
+                const double *params, size_t n_params, const uint64_t *z_masks,
+                const double *coeffs, size_t n_terms, const size_t *ckpt_at,
+                size_t n_ckpt, double *expval, double *grad);
+
+/* ---- batched execution ------------------------------------------------------ */
+
+typedef struct msv_circuit {
+    int32_t n_qubits;
+    const msv_gate *gates;
+    size_t n_gates;
+    uint64_t init_basis;
+} msv_circuit;
+
+typedef struct msv_batch_opts {
+    int32_t autotune;        /* 1 = choose fusion width and tile per circuit   */
+    int32_t k_max;           /* used when autotune = 0                          */
+    int32_t log2_tile;       /* used when autotune = 0 (0 = automatic)          */
+    int32_t mma_precision;   /* enum msv_mma                                    */
+} msv_batch_opts;
+
+/* Run count circuits in one persistent launch per step. amps_out[i] (host,
+ * 2^n_i complex of dtype) may be NULL to skip the copy; stats_out aggregates. */
+int msv_batch_run(const msv_circuit *circuits, size_t count, int dtype, double eb,
+                  const msv_batch_opts *opts, void *const *amps_out,
+                  msv_stats *stats_out);
+/* Adjoint gradients of one ansatz for n_sets parameter sets (params is
+ * n_sets x n_params, row-major); expvals[n_sets], grads[n_sets x n_params]. */
+int msv_batch_adjoint(const msv_circuit *ansatz, const double *params, size_t n_sets,
+                      size_t n_params, const uint64_t *z_masks, const double *coeffs,
+                      size_t n_terms, const size_t *ckpt_at, size_t n_ckpt, int dtype,
+                      double eb, double *expvals, double *grads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSV_C_ABI_H_ */

@@ -1,0 +1,503 @@
+// Kernels around the pass: basis-state init, FP64 reductions for
+// measurement / expectation / fidelity, range decode, and the canonical chunk
+// format (encode into per-block slots, per-chunk scan, assembly, parsing).
+#include <hip/hip_runtime.h>
+
+#include "codec_device.h"
+#include "kernels.h"
+
+namespace msv {
+
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using V = float2; };
+template <> struct Vec2<double> { using V = double2; };
+
+static __device__ __forceinline__ uint64_t bidx(const BlockStore &s, uint64_t B)
+{
+    if (!s.chunk_slot) return B;
+    const uint64_t nbm = (1ull << s.log2_nb) - 1;
+    return ((uint64_t)s.chunk_slot[B >> s.log2_nb] << s.log2_nb) | (B & nbm);
+}
+
+// Decode one 64-value stream block with the calling wave; lane i gets value i.
+template <typename T>
+static __device__ __forceinline__ T decode_one(const BlockStore &s, uint64_t B, double step)
+{
+    const uint64_t bi = bidx(s, B);
+    const uint32_t W = s.W[bi];
+    const int32_t A = s.A[bi];
+    uint64_t mine = 0;
+    if (W) {
+        const uint64_t off = s.OFF[bi];
+        if (lane_id() < W) mine = s.heap[off + lane_id()];
+    }
+    return dequantize<T>(unpack_codes(mine, W, A), step);
+}
+
+// ------------------------------------------------------------------ init
+
+template <typename T>
+__global__ __launch_bounds__(64) void init_basis_block_kernel(BlockStore st, uint64_t index,
+                                                              double inv_step)
+{
+    const uint32_t lane = lane_id();
+    bool bad = false;
+    const T x = lane == (uint32_t)(index & 63u) ? (T)1 : (T)0;
+    const int32_t q = quantize<T>(x, inv_step, bad);
+    const uint32_t u = residual_zigzag(q);
+    const uint32_t W = block_width(u);
+    const int32_t A = __builtin_amdgcn_readlane(q, 0);
+    const uint64_t mine = pack_planes(u, W);
+    const uint64_t bi = bidx(st, 2 * (index >> 6));
+    if (lane < W) st.heap[lane] = mine;
+    if (lane == 0) { st.W[bi] = (uint8_t)W; st.A[bi] = A; st.OFF[bi] = 0; }
+}
+
+hipError_t launch_init_basis_block(bool is_double, BlockStore st, uint64_t index, double inv_step,
+                                   hipStream_t stream)
+{
+    if (is_double)
+        hipLaunchKernelGGL(init_basis_block_kernel<double>, dim3(1), dim3(64), 0, stream, st, index, inv_step);
+    else
+        hipLaunchKernelGGL(init_basis_block_kernel<float>, dim3(1), dim3(64), 0, stream, st, index, inv_step);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- reductions
+
+constexpr int kRedGroups = 2048;
+
+template <typename T, bool COMP>
+__global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, BlockStore st, double step,
+                                                          ReduceArgs a)
+{
+    using V2 = typename Vec2<T>::V;
+    constexpr int NW = kThreads / 64;
+    __shared__ double sacc[4][NW];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t nab = a.amp_count >> 6, first = a.amp_begin >> 6;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (uint64_t k = (uint64_t)blockIdx.x * NW + wave; k < nab; k += (uint64_t)gridDim.x * NW) {
+        const uint64_t G = first + k;
+        double xr, xi;
+        if (COMP) {
+            xr = (double)decode_one<T>(st, 2 * G, step);
+            xi = (double)decode_one<T>(st, 2 * G + 1, step);
+        } else {
+            const V2 v = ((const V2 *)amps)[(G << 6) | (uint64_t)lane];
+            xr = v.x;
+            xi = v.y;
+        }
+        xr *= a.scale;
+        xi *= a.scale;
+        const uint64_t i = (G << 6) | (uint64_t)lane;
+        const double p = xr * xr + xi * xi;
+        acc[0] += p;
+        if (a.kind == RED_PROB1) {
+            if ((i >> a.qubit) & 1ull) acc[1] += p;
+        } else if (a.kind == RED_EXPZ) {
+            double v = 0.0;
+            for (int t = 0; t < a.n_terms; ++t)
+                v += (__popcll(i & a.masks[t]) & 1) ? -a.coeffs[t] : a.coeffs[t];
+            acc[1] += p * v;
+        } else if (a.kind == RED_OVERLAP) {
+            const uint64_t r = i - a.amp_begin;
+            const double rr = a.ref[2 * r], ri = a.ref[2 * r + 1];
+            acc[1] += rr * xr + ri * xi;   // Re(conj(ref) psi)
+            acc[2] += rr * xi - ri * xr;   // Im(conj(ref) psi)
+            acc[3] += rr * rr + ri * ri;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const double s = wave_sum_f64(acc[j]);
+        if (lane == 0) sacc[j][wave] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s += sacc[threadIdx.x][w];
+        a.partials[4 * blockIdx.x + threadIdx.x] = s;
+    }
+}
+
+hipError_t launch_reduce(bool is_double, bool compressed, const void *amps, BlockStore st,
+                         double step, const ReduceArgs &a, int *n_groups, hipStream_t stream)
+{
+    const uint64_t nab = a.amp_count >> 6;
+    uint64_t g = (nab + 3) / 4;
+    if (g > (uint64_t)kRedGroups) g = kRedGroups;
+    if (g == 0) g = 1;
+    *n_groups = (int)g;
+    const dim3 grid((unsigned)g), block(kThreads);
+    if (is_double) {
+        if (compressed) hipLaunchKernelGGL((reduce_kernel<double, true>), grid, block, 0, stream, amps, st, step, a);
+        else hipLaunchKernelGGL((reduce_kernel<double, false>), grid, block, 0, stream, amps, st, step, a);
+    } else {
+        if (compressed) hipLaunchKernelGGL((reduce_kernel<float, true>), grid, block, 0, stream, amps, st, step, a);
+        else hipLaunchKernelGGL((reduce_kernel<float, false>), grid, block, 0, stream, amps, st, step, a);
+    }
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kThreads) void reduce_final_kernel(const double *partials, int n, double *out)
+{
+    __shared__ double s[4][kThreads];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int g = threadIdx.x; g < n; g += kThreads)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] += partials[4 * g + j];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s[j][threadIdx.x] = acc[j];
+    __syncthreads();
+    for (int w = kThreads / 2; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) s[j][threadIdx.x] += s[j][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) out[threadIdx.x] = s[threadIdx.x][0];
+}
+
+hipError_t launch_reduce_final(const double *partials, int n_groups, double *out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(kThreads), 0, stream, partials, n_groups, out);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kThreads) void pass_stats_kernel(const double *part, const uint64_t *offs,
+                                                              double *out)
+{
+    __shared__ double sn[kThreads], se[kThreads], sw[kThreads];
+    const int p = blockIdx.x;
+    double a = 0.0, e = 0.0, w = 0.0;
+    for (uint64_t i = offs[p] + threadIdx.x; i < offs[p + 1]; i += kThreads) {
+        a += part[3 * i];
+        e = fmax(e, part[3 * i + 1]);
+        w += part[3 * i + 2];
+    }
+    sn[threadIdx.x] = a;
+    se[threadIdx.x] = e;
+    sw[threadIdx.x] = w;
+    __syncthreads();
+    for (int h = kThreads / 2; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            sn[threadIdx.x] += sn[threadIdx.x + h];
+            se[threadIdx.x] = fmax(se[threadIdx.x], se[threadIdx.x + h]);
+            sw[threadIdx.x] += sw[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { out[3 * p] = sn[0]; out[3 * p + 1] = se[0]; out[3 * p + 2] = sw[0]; }
+}
+
+hipError_t launch_pass_stats(const double *part, const uint64_t *pass_offsets, int n_passes, double *out,
+                             hipStream_t stream)
+{
+    if (n_passes <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pass_stats_kernel, dim3(n_passes), dim3(kThreads), 0, stream, part, pass_offsets, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ range decode
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void decode_range_kernel(BlockStore st, double step, double scale,
+                                                                uint64_t first, uint64_t nab, void *out)
+{
+    using V2 = typename Vec2<T>::V;
+    constexpr int NW = kThreads / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (uint64_t k = (uint64_t)blockIdx.x * NW + wave; k < nab; k += (uint64_t)gridDim.x * NW) {
+        const uint64_t G = first + k;
+        V2 v;
+        v.x = decode_one<T>(st, 2 * G, step);
+        v.y = decode_one<T>(st, 2 * G + 1, step);
+        if (scale != 1.0) { v.x = (T)(v.x * (T)scale); v.y = (T)(v.y * (T)scale); }
+        ((V2 *)out)[(k << 6) | (uint64_t)lane] = v;
+    }
+}
+
+hipError_t launch_decode_range(bool is_double, BlockStore st, double step, double scale, uint64_t amp_begin,
+                               uint64_t amp_count, void *out, hipStream_t stream)
+{
+    const uint64_t nab = amp_count >> 6;
+    uint64_t g = (nab + 3) / 4;
+    if (g > 65536) g = 65536;
+    if (g == 0) return hipSuccess;
+    if (is_double)
+        hipLaunchKernelGGL(decode_range_kernel<double>, dim3((unsigned)g), dim3(kThreads), 0, stream, st, step,
+                           scale, amp_begin >> 6, nab, out);
+    else
+        hipLaunchKernelGGL(decode_range_kernel<float>, dim3((unsigned)g), dim3(kThreads), 0, stream, st, step,
+                           scale, amp_begin >> 6, nab, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------- canonical chunk format
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void encode_chunks_kernel(const T *vals, uint64_t n_blocks,
+                                                                 double inv_step, double step, uint8_t *W,
+                                                                 int32_t *A, uint64_t *slots,
+                                                                 unsigned long long *err_bits, uint32_t *flags)
+{
+    constexpr int NW = kThreads / 64;
+    const uint32_t lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    double err = 0.0;
+    bool bad = false;
+    for (uint64_t b = (uint64_t)blockIdx.x * NW + wave; b < n_blocks; b += (uint64_t)gridDim.x * NW) {
+        const uint64_t j = b >> 1, p = b & 1;
+        const T x = vals[2 * ((j << 6) | lane) + p];
+        const int32_t q = quantize<T>(x, inv_step, bad);
+        const T xr = dequantize<T>(q, step);
+        err = fmax(err, __builtin_fabs((double)x - (double)xr));
+        const uint32_t u = residual_zigzag(q);
+        const uint32_t w = block_width(u);
+        const uint64_t mine = pack_planes(u, w);
+        const int32_t a0 = __builtin_amdgcn_readlane(q, 0);
+        if (lane < w) slots[b * 32 + lane] = mine;
+        if (lane == 0) { W[b] = (uint8_t)w; A[b] = a0; }
+    }
+    err = wave_max_f64(err);
+    if (lane == 0) atomicMax(err_bits, (unsigned long long)__double_as_longlong(err));
+    if (bad) atomicOr(flags, 1u);
+}
+
+hipError_t launch_encode_chunks(bool is_double, const void *vals, uint64_t n_blocks_total, double inv_step,
+                                uint8_t *W, int32_t *A, uint64_t *slot_words, double *err_max_bits,
+                                uint32_t *flags, double step, hipStream_t stream)
+{
+    uint64_t g = (n_blocks_total + 3) / 4;
+    if (g > 65536) g = 65536;
+    if (g == 0) return hipSuccess;
+    unsigned long long *eb = reinterpret_cast<unsigned long long *>(err_max_bits);
+    if (is_double)
+        hipLaunchKernelGGL(encode_chunks_kernel<double>, dim3((unsigned)g), dim3(kThreads), 0, stream,
+                           (const double *)vals, n_blocks_total, inv_step, step, W, A, slot_words, eb, flags);
+    else
+        hipLaunchKernelGGL(encode_chunks_kernel<float>, dim3((unsigned)g), dim3(kThreads), 0, stream,
+                           (const float *)vals, n_blocks_total, inv_step, step, W, A, slot_words, eb, flags);
+    return hipGetLastError();
+}
+
+static __device__ __forceinline__ uint64_t pad8(uint64_t x) { return (x + 7) & ~7ull; }
+
+// Block-wide exclusive scan of one uint64 per thread; returns the total.
+static __device__ uint64_t block_exclusive_scan(uint64_t v, uint64_t *ex, uint64_t *sbuf)
+{
+    sbuf[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < kThreads; off <<= 1) {
+        const uint64_t t = threadIdx.x >= (unsigned)off ? sbuf[threadIdx.x - off] : 0ull;
+        __syncthreads();
+        sbuf[threadIdx.x] += t;
+        __syncthreads();
+    }
+    const uint64_t incl = sbuf[threadIdx.x];
+    const uint64_t total = sbuf[kThreads - 1];
+    __syncthreads();
+    *ex = incl - v;
+    return total;
+}
+
+__global__ __launch_bounds__(kThreads) void scan_chunks_kernel(const uint8_t *W, const int32_t *A, uint64_t nb,
+                                                               uint32_t *off, uint64_t *sizes, uint32_t *kinds,
+                                                               uint32_t *flags)
+{
+    __shared__ uint64_t sbuf[kThreads];
+    __shared__ int snz;
+    const uint64_t c = blockIdx.x;
+    const uint8_t *w = W + c * nb;
+    const int32_t *a = A + c * nb;
+    const uint64_t per = (nb + kThreads - 1) / kThreads;
+    const uint64_t b0 = threadIdx.x * per, b1 = b0 + per < nb ? b0 + per : nb;
+    if (threadIdx.x == 0) snz = 0;
+    uint64_t s = 0;
+    bool nz = false, badw = false;
+    for (uint64_t b = b0; b < b1; ++b) {
+        const uint32_t wb = w[b];
+        s += wb;
+        nz |= wb != 0 || a[b] != 0;
+        badw |= wb > 32;
+    }
+    if (badw) atomicOr(flags, 2u);
+    __syncthreads();
+    if (nz) snz = 1;
+    uint64_t ex;
+    const uint64_t total = block_exclusive_scan(s, &ex, sbuf);
+    for (uint64_t b = b0; b < b1; ++b) {
+        off[c * nb + b] = (uint32_t)ex;
+        ex += w[b];
+    }
+    if (threadIdx.x == 0) {
+        const bool general = snz != 0;
+        kinds[c] = general ? 1u : 0u;
+        sizes[c] = general ? 32 + pad8(nb) + pad8(4 * nb) + 8 * total : 32;
+    }
+}
+
+hipError_t launch_scan_chunks(const uint8_t *W, const int32_t *A, uint64_t nb, uint64_t n_chunks, uint32_t *off,
+                              uint64_t *sizes, uint32_t *kinds, uint32_t *flags, hipStream_t stream)
+{
+    if (n_chunks == 0) return hipSuccess;
+    hipLaunchKernelGGL(scan_chunks_kernel, dim3((unsigned)n_chunks), dim3(kThreads), 0, stream, W, A, nb, off,
+                       sizes, kinds, flags);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kThreads) void scan_sizes_kernel(const uint64_t *sizes, uint64_t n, uint64_t *offsets)
+{
+    __shared__ uint64_t sbuf[kThreads];
+    const uint64_t per = (n + kThreads - 1) / kThreads;
+    const uint64_t i0 = threadIdx.x * per, i1 = i0 + per < n ? i0 + per : n;
+    uint64_t s = 0;
+    for (uint64_t i = i0; i < i1; ++i) s += (sizes[i] + 255) & ~255ull;
+    uint64_t ex;
+    const uint64_t total = block_exclusive_scan(s, &ex, sbuf);
+    for (uint64_t i = i0; i < i1; ++i) {
+        offsets[i] = ex;
+        ex += (sizes[i] + 255) & ~255ull;
+    }
+    if (threadIdx.x == 0) offsets[n] = total;
+}
+
+hipError_t launch_scan_sizes(const uint64_t *sizes, uint64_t n, uint64_t *offsets, hipStream_t stream)
+{
+    hipLaunchKernelGGL(scan_sizes_kernel, dim3(1), dim3(kThreads), 0, stream, sizes, n, offsets);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kThreads) void assemble_chunks_kernel(int dtype, int log2c, double eb,
+                                                                   const uint8_t *W, const int32_t *A,
+                                                                   const uint32_t *src_off, const uint64_t *src,
+                                                                   const uint32_t *dst_off, const uint64_t *sizes,
+                                                                   const uint32_t *kinds, const uint64_t *offsets,
+                                                                   uint64_t nb, uint64_t n_chunks, uint8_t *out)
+{
+    constexpr int NW = kThreads / 64;
+    const uint32_t lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    const uint64_t total_blocks = nb * n_chunks;
+    const uint64_t a_off = 32 + pad8(nb), p_off = a_off + pad8(4 * nb);
+    for (uint64_t gb = (uint64_t)blockIdx.x * NW + wave; gb < total_blocks; gb += (uint64_t)gridDim.x * NW) {
+        const uint64_t c = gb / nb, b = gb - c * nb;
+        uint8_t *o = out + offsets[c];
+        const bool general = kinds[c] != 0;
+        if (b == 0 && lane < 8) {
+            // header as eight 32-bit words
+            uint32_t v = 0;
+            switch (lane) {
+            case 0: v = 0x4356534Du; break;
+            case 1: v = 1u | ((general ? 1u : 0u) << 8) | ((uint32_t)log2c << 16) | ((uint32_t)dtype << 24); break;
+            case 2: v = (uint32_t)(__double_as_longlong(eb) & 0xffffffffull); break;
+            case 3: v = (uint32_t)((unsigned long long)__double_as_longlong(eb) >> 32); break;
+            case 4: v = (uint32_t)(sizes[c] & 0xffffffffull); break;
+            case 5: v = (uint32_t)(sizes[c] >> 32); break;
+            case 6: v = (uint32_t)nb; break;
+            default: v = 0; break;
+            }
+            reinterpret_cast<uint32_t *>(o)[lane] = v;
+        }
+        if (!general) continue;
+        if (b == 0) {
+            // zero padding after W and after A
+            for (uint64_t i = 32 + nb + lane; i < a_off; i += 64) o[i] = 0;
+            for (uint64_t i = a_off + 4 * nb + lane; i < p_off; i += 64) o[i] = 0;
+        }
+        const uint32_t w = W[gb];
+        if (lane == 0) {
+            o[32 + b] = (uint8_t)w;
+            reinterpret_cast<int32_t *>(o + a_off)[b] = A[gb];
+        }
+        if (lane < w) {
+            const uint64_t d = p_off / 8 + dst_off[gb] + lane;
+            const uint64_t so = src_off ? (uint64_t)src_off[gb] : gb * 32;
+            reinterpret_cast<uint64_t *>(o)[d] = src[so + lane];
+        }
+    }
+}
+
+hipError_t launch_assemble_chunks(int dtype, int log2c, double eb, const uint8_t *W, const int32_t *A,
+                                  const uint32_t *src_off, const uint64_t *src_heap, const uint32_t *dst_off,
+                                  const uint64_t *sizes, const uint32_t *kinds, const uint64_t *offsets,
+                                  uint64_t n_chunks, uint8_t *out, hipStream_t stream)
+{
+    const uint64_t nb = (2ull << log2c) / 64;
+    uint64_t g = (nb * n_chunks + 3) / 4;
+    if (g > 65536) g = 65536;
+    if (g == 0) return hipSuccess;
+    hipLaunchKernelGGL(assemble_chunks_kernel, dim3((unsigned)g), dim3(kThreads), 0, stream, dtype, log2c, eb, W, A,
+                       src_off, src_heap, dst_off, sizes, kinds, offsets, nb, n_chunks, out);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kThreads) void parse_chunks_kernel(const uint8_t *base, const uint64_t *offsets,
+                                                                const uint64_t *staged, int log2c, uint64_t nb,
+                                                                uint8_t *W, int32_t *A, uint32_t *OFF,
+                                                                uint32_t *flags)
+{
+    __shared__ uint64_t sbuf[kThreads];
+    __shared__ int sbad;
+    const uint64_t c = blockIdx.x;
+    const uint8_t *o = base + offsets[c];
+    const uint64_t have = staged[c];
+    const uint64_t a_off = 32 + pad8(nb), p_off = a_off + pad8(4 * nb);
+    // header first: nothing past it is read unless the header is consistent
+    // with the bytes actually staged for this chunk
+    bool hdr_bad = have < 32;
+    uint32_t kind = 0;
+    uint64_t total = 0;
+    if (!hdr_bad) {
+        const uint32_t *h = reinterpret_cast<const uint32_t *>(o);
+        const uint32_t meta = h[1];
+        kind = (meta >> 8) & 0xffu;
+        total = (uint64_t)h[4] | ((uint64_t)h[5] << 32);
+        hdr_bad = h[0] != 0x4356534Du || (meta & 0xffu) != 1u || kind > 1u ||
+                  ((meta >> 16) & 0xffu) != (uint32_t)log2c || h[6] != (uint32_t)nb || h[7] != 0u ||
+                  total != have || (kind == 0 && total != 32) || (kind == 1 && total < p_off);
+    }
+    const bool general = !hdr_bad && kind == 1;
+    if (threadIdx.x == 0) sbad = hdr_bad ? 1 : 0;
+    const uint64_t per = (nb + kThreads - 1) / kThreads;
+    const uint64_t b0 = threadIdx.x * per, b1 = b0 + per < nb ? b0 + per : nb;
+    uint64_t s = 0;
+    bool wbad = false;
+    for (uint64_t b = b0; b < b1; ++b) {
+        const uint32_t w = general ? o[32 + b] : 0u;
+        wbad |= w > 32;
+        s += w;
+    }
+    __syncthreads();
+    if (wbad) sbad = 1;
+    uint64_t ex;
+    const uint64_t words = block_exclusive_scan(s, &ex, sbuf);
+    if (threadIdx.x == 0 && general && p_off + 8 * words != total) sbad = 1;
+    __syncthreads();
+    const bool ok = general && sbad == 0;
+    const uint64_t pay0 = (offsets[c] + p_off) / 8;
+    for (uint64_t b = b0; b < b1; ++b) {
+        const uint64_t gb = c * nb + b;
+        const uint32_t w = ok ? o[32 + b] : 0u;
+        W[gb] = (uint8_t)w;
+        A[gb] = ok ? reinterpret_cast<const int32_t *>(o + a_off)[b] : 0;
+        OFF[gb] = ok ? (uint32_t)(pay0 + ex) : 0u;
+        ex += w;
+    }
+    if (threadIdx.x == 0 && sbad) atomicOr(flags, 4u);
+}
+
+hipError_t launch_parse_chunks(const uint8_t *base, const uint64_t *offsets, const uint64_t *staged,
+                               uint64_t n_chunks, int log2c, uint8_t *W, int32_t *A, uint32_t *OFF,
+                               uint32_t *flags, hipStream_t stream)
+{
+    if (n_chunks == 0) return hipSuccess;
+    const uint64_t nb = (2ull << log2c) / 64;
+    hipLaunchKernelGGL(parse_chunks_kernel, dim3((unsigned)n_chunks), dim3(kThreads), 0, stream, base, offsets,
+                       staged, log2c, nb, W, A, OFF, flags);
+    return hipGetLastError();
+}
+
+}  // namespace msv

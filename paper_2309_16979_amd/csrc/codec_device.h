@@ -1,0 +1,129 @@
+// Wave-level building blocks of the chunk codec on gfx950 (wave64).
+//
+// One 64-lane wave handles one 64-value block of one plane: lane i holds value
+// i. Prediction residuals use a DPP wave shift, the decode prefix sum a DPP
+// Hillis-Steele scan within rows of 16 plus two row broadcasts, the width an
+// OR reduction, and bit-plane packing one ballot per plane.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace msv {
+
+template <int CTRL, int ROW_MASK, int BANK_MASK, bool BOUND_ZERO>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, BANK_MASK, BOUND_ZERO);
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Inclusive prefix sum over the 64 lanes (uint32 wrap-around arithmetic).
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t x)
+{
+    x += dpp_u32<0x111, 0xf, 0xf, true>(x);   // row_shr:1
+    x += dpp_u32<0x112, 0xf, 0xf, true>(x);   // row_shr:2
+    x += dpp_u32<0x114, 0xf, 0xf, true>(x);   // row_shr:4
+    x += dpp_u32<0x118, 0xf, 0xf, true>(x);   // row_shr:8
+    x += dpp_u32<0x142, 0xa, 0xf, false>(x);  // row_bcast:15 -> rows 1, 3
+    x += dpp_u32<0x143, 0xc, 0xf, false>(x);  // row_bcast:31 -> rows 2, 3
+    return x;
+}
+
+// Bitwise OR of all 64 lanes, returned uniformly.
+__device__ __forceinline__ uint32_t wave_or(uint32_t x)
+{
+    x |= dpp_u32<0x111, 0xf, 0xf, true>(x);
+    x |= dpp_u32<0x112, 0xf, 0xf, true>(x);
+    x |= dpp_u32<0x114, 0xf, 0xf, true>(x);
+    x |= dpp_u32<0x118, 0xf, 0xf, true>(x);
+    x |= dpp_u32<0x142, 0xa, 0xf, false>(x);
+    x |= dpp_u32<0x143, 0xc, 0xf, false>(x);
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+// Value of lane i-1 (0 for lane 0).
+__device__ __forceinline__ uint32_t wave_shift_up1(uint32_t x)
+{
+    return dpp_u32<0x138, 0xf, 0xf, true>(x);  // wave_shr:1
+}
+
+// Code of this lane's value: q = rint(x * inv_step) in FP64, round half to
+// even. `bad` is set when x is not finite or |q| > 2^30 - 1 (the code is then 0).
+template <typename T>
+__device__ __forceinline__ int32_t quantize(T x, double inv_step, bool &bad)
+{
+    const double r = __builtin_rint((double)x * inv_step);
+    const bool ok = __builtin_fabs(r) <= 1073741823.0;
+    bad |= !ok;
+    return ok ? (int32_t)r : 0;
+}
+
+// Decoded value of a code: (T)((double)q * step).
+template <typename T>
+__device__ __forceinline__ T dequantize(int32_t q, double step)
+{
+    return (T)((double)q * step);
+}
+
+// Zigzag of the Lorenzo-1 residual d_i = q_i - q_(i-1), d_0 = 0.
+__device__ __forceinline__ uint32_t residual_zigzag(int32_t q)
+{
+    const uint32_t prev = wave_shift_up1((uint32_t)q);
+    const int32_t d = lane_id() == 0 ? 0 : (int32_t)((uint32_t)q - prev);
+    return ((uint32_t)d << 1) ^ (uint32_t)(d >> 31);
+}
+
+// Bits needed for every lane's u (0..32), uniform.
+__device__ __forceinline__ uint32_t block_width(uint32_t u)
+{
+    const uint32_t o = wave_or(u);
+    return o ? 32u - (uint32_t)__builtin_clz(o) : 0u;
+}
+
+// Lane k (< W) receives bit-plane word k: bit i = bit k of lane i's u.
+__device__ __forceinline__ uint64_t pack_planes(uint32_t u, uint32_t W)
+{
+    uint64_t mine = 0;
+    const uint32_t lane = lane_id();
+    for (uint32_t k = 0; k < W; ++k) {
+        const uint64_t bal = __builtin_amdgcn_ballot_w64(((u >> k) & 1u) != 0u);
+        if (lane == k) mine = bal;
+    }
+    return mine;
+}
+
+// Inverse of pack_planes + prediction: code of this lane's value. `mine` is the
+// word this lane loaded (word lane, lanes >= W hold anything).
+__device__ __forceinline__ int32_t unpack_codes(uint64_t mine, uint32_t W, int32_t A)
+{
+    if (W == 0) return A;
+    const uint32_t lane = lane_id();
+    const uint32_t sh = lane & 31u;
+    const bool hi = lane >= 32u;
+    uint32_t u = 0;
+    for (uint32_t k = 0; k < W; ++k) {
+        const uint32_t lo_w = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mine, (int)k);
+        const uint32_t hi_w = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mine >> 32), (int)k);
+        const uint32_t w = hi ? hi_w : lo_w;
+        u |= ((w >> sh) & 1u) << k;
+    }
+    const uint32_t d = (u >> 1) ^ (0u - (u & 1u));
+    return (int32_t)((uint32_t)A + wave_inclusive_sum(d));
+}
+
+// FP64 sum over the 64 lanes, returned to every lane (butterfly: the same
+// order on every call, so the result is reproducible).
+__device__ __forceinline__ double wave_sum_f64(double x)
+{
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+__device__ __forceinline__ double wave_max_f64(double x)
+{
+    for (int off = 32; off >= 1; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
+    return x;
+}
+
+}  // namespace msv

@@ -1,0 +1,119 @@
+// Host-side launchers of the HIP kernels (defined in *.hip).
+#pragma once
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "device_ops.h"
+
+namespace msv {
+
+// Compressed blocks addressed by global stream block B = 2 * (amp >> 6) + plane.
+// With chunk_slot == nullptr the arrays are indexed by B directly; otherwise
+// block B lives at slot chunk_slot[B >> log2_nb] of the arrays (host store).
+struct BlockStore {
+    uint8_t *W;
+    int32_t *A;
+    uint32_t *OFF;      // word offset of the block's payload in heap
+    uint64_t *heap;
+    const uint32_t *chunk_slot;
+    int32_t log2_nb;    // log2(stream blocks per chunk)
+};
+
+struct PassBuffers {
+    void *amps_in;               // plain load (interleaved complex)
+    void *amps_out;              // plain store
+    BlockStore in, out;          // compressed load / store
+    uint64_t slot_tile0;         // tile whose heap slot is slot 0
+    double inv_step, step;       // 1 / (2 eb) and 2 eb
+    double scale;                // multiplies decoded values (renormalisation)
+    const double *scale_src;     // if set: scale = 1 / sqrt(*scale_src) (previous pass norm)
+    double *part;                // per workgroup: sum |x|^2 (pre-encode), max |x - x'|,
+                                 // payload words written (3 doubles)
+    uint32_t *flags;             // bit 0: code out of range / non-finite value
+    int32_t check_err;
+    const OpDesc *ops;
+    const void *pool;            // matrix pool, complex of the state's real type
+};
+
+// Launch one pass over geo.n_tiles tiles. is_double selects complex128.
+// load_c / store_c select compressed (true) or plain amplitudes on each side.
+hipError_t launch_pass(bool is_double, bool load_c, bool store_c, const PassGeom &geo,
+                       const PassBuffers &buf, hipStream_t stream);
+
+// Encode the single nonzero block of |index> (value 1 at amplitude index) into
+// the store; every other block must already read W = 0, A = 0.
+hipError_t launch_init_basis_block(bool is_double, BlockStore st, uint64_t index,
+                                   double inv_step, hipStream_t stream);
+
+enum ReduceKind : int32_t { RED_NORM = 0, RED_PROB1 = 1, RED_EXPZ = 2, RED_OVERLAP = 3 };
+
+struct ReduceArgs {
+    int32_t kind;
+    int32_t qubit;
+    uint64_t amp_begin, amp_count;   // amplitude range (multiples of 64)
+    const uint64_t *masks;           // RED_EXPZ
+    const double *coeffs;
+    int32_t n_terms;
+    const double *ref;               // RED_OVERLAP: complex128 for amps [amp_begin, +count)
+    double *partials;                // 4 doubles per workgroup
+    double scale;
+};
+
+// Per-workgroup partials of an FP64 reduction over decoded amplitudes.
+// Returns the number of workgroups used.
+hipError_t launch_reduce(bool is_double, bool compressed, const void *amps, BlockStore st,
+                         double step, const ReduceArgs &a, int *n_groups, hipStream_t stream);
+// out[j] = sum_g partials[4 g + j] (fixed order), j < 4.
+hipError_t launch_reduce_final(const double *partials, int n_groups, double *out,
+                               hipStream_t stream);
+// Pass statistics from the per-workgroup triples of passes [0, n_passes):
+// out[3p] = sum of norms, out[3p+1] = max error, out[3p+2] = sum of words.
+// Workgroups of pass p are part[3 * pass_offsets[p] ...].
+hipError_t launch_pass_stats(const double *part, const uint64_t *pass_offsets, int n_passes,
+                             double *out, hipStream_t stream);
+
+// Decode amplitudes [amp_begin, amp_begin + amp_count) (multiples of 64) into out.
+hipError_t launch_decode_range(bool is_double, BlockStore st, double step, double scale,
+                               uint64_t amp_begin, uint64_t amp_count, void *out,
+                               hipStream_t stream);
+
+// ---- canonical chunk format (codec API, export, host store) ----------------
+
+// Encode n_chunks chunks of interleaved complex values (contiguous) into
+// per-block slots: W[b], A[b], and payload words at slot_words[b * 32].
+hipError_t launch_encode_chunks(bool is_double, const void *vals, uint64_t n_blocks_total,
+                                double inv_step, uint8_t *W, int32_t *A, uint64_t *slot_words,
+                                double *err_max_bits, uint32_t *flags, double step,
+                                hipStream_t stream);
+
+// Per chunk c (n_chunks of nb blocks): exclusive scan of W into off[] (words,
+// relative to the chunk payload start) and the canonical chunk size in
+// sizes[c]; kinds[c] = 0 when every W and A is zero. flags bit 1 = a W > 32.
+hipError_t launch_scan_chunks(const uint8_t *W, const int32_t *A, uint64_t nb, uint64_t n_chunks,
+                              uint32_t *off, uint64_t *sizes, uint32_t *kinds, uint32_t *flags,
+                              hipStream_t stream);
+
+// Exclusive scan of sizes (rounded up to 256 bytes) into offsets[n], total at offsets[n].
+hipError_t launch_scan_sizes(const uint64_t *sizes, uint64_t n, uint64_t *offsets,
+                             hipStream_t stream);
+
+// Write canonical chunks: header, W, A and payload copied from src_heap at
+// src_off[b] (words; nullptr = per-block slots of 32 words) for each block.
+// Chunk c goes to out + offsets[c] (offsets 256-byte aligned).
+hipError_t launch_assemble_chunks(int dtype, int log2c, double eb, const uint8_t *W,
+                                  const int32_t *A, const uint32_t *src_off,
+                                  const uint64_t *src_heap, const uint32_t *dst_off,
+                                  const uint64_t *sizes, const uint32_t *kinds,
+                                  const uint64_t *offsets, uint64_t n_chunks, uint8_t *out,
+                                  hipStream_t stream);
+
+// Parse staged canonical chunks (chunk c at base + offsets[c], staged[c]
+// bytes, offsets 8-byte aligned) into W/A/OFF arrays of slot c (OFF relative to
+// base, in words). A chunk whose header, widths or length disagree is read as
+// all zeros and sets flags bit 2; nothing beyond staged[c] bytes is read.
+hipError_t launch_parse_chunks(const uint8_t *base, const uint64_t *offsets, const uint64_t *staged,
+                               uint64_t n_chunks, int log2c, uint8_t *W, int32_t *A, uint32_t *OFF,
+                               uint32_t *flags, hipStream_t stream);
+
+}  // namespace msv

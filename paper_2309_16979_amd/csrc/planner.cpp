@@ -1,0 +1,462 @@
+#include "planner.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace msv {
+
+namespace {
+
+const double kPi = 3.14159265358979323846;
+
+cd expi(double a) { return cd(std::cos(a), std::sin(a)); }
+
+bool is_diagonal(const std::vector<cd> &m, int d)
+{
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c)
+            if (r != c && m[r * d + c] != cd(0.0)) return false;
+    return true;
+}
+
+std::vector<cd> dagger(const std::vector<cd> &m, int d)
+{
+    std::vector<cd> o(d * d);
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) o[c * d + r] = std::conj(m[r * d + c]);
+    return o;
+}
+
+// Matrix of a k-qubit op (qubits q, D x D) embedded on the ordered qubit list Q
+// (a superset of q).
+std::vector<cd> embed(const std::vector<int> &q, const std::vector<cd> &m, const std::vector<int> &Q)
+{
+    const int k = (int)q.size(), K = (int)Q.size(), d = 1 << k, D = 1 << K;
+    std::vector<int> at(k);
+    int qmask = 0;
+    for (int i = 0; i < k; ++i) {
+        at[i] = (int)(std::find(Q.begin(), Q.end(), q[i]) - Q.begin());
+        qmask |= 1 << at[i];
+    }
+    auto sub = [&](int s) {
+        int v = 0;
+        for (int i = 0; i < k; ++i) v |= ((s >> at[i]) & 1) << i;
+        return v;
+    };
+    std::vector<cd> e((size_t)D * D, cd(0.0));
+    for (int r = 0; r < D; ++r)
+        for (int c = 0; c < D; ++c)
+            if ((r & ~qmask) == (c & ~qmask)) e[(size_t)r * D + c] = m[sub(r) * d + sub(c)];
+    return e;
+}
+
+std::vector<cd> matmul(const std::vector<cd> &a, const std::vector<cd> &b, int D)
+{
+    std::vector<cd> o((size_t)D * D, cd(0.0));
+    for (int r = 0; r < D; ++r)
+        for (int k = 0; k < D; ++k) {
+            const cd x = a[(size_t)r * D + k];
+            if (x == cd(0.0)) continue;
+            for (int c = 0; c < D; ++c) o[(size_t)r * D + c] += x * b[(size_t)k * D + c];
+        }
+    return o;
+}
+
+std::vector<int> unite(const std::vector<int> &a, const std::vector<int> &b)
+{
+    std::vector<int> o = a;
+    for (int x : b)
+        if (std::find(o.begin(), o.end(), x) == o.end()) o.push_back(x);
+    return o;
+}
+
+bool subset(const std::vector<int> &a, const std::vector<int> &b)
+{
+    for (int x : a)
+        if (std::find(b.begin(), b.end(), x) == b.end()) return false;
+    return true;
+}
+
+}  // namespace
+
+int gate_to_prim(const msv_gate &g, int n, bool inverse, Prim &p, std::string &err)
+{
+    const bool two = g.kind == MSV_CX || g.kind == MSV_CZ || g.kind == MSV_CP || g.kind == MSV_SWAP ||
+                     g.kind == MSV_U2;
+    if (g.kind > MSV_U2) { err = "unknown gate kind"; return MSV_E_ARG; }
+    if (g.q0 < 0 || g.q0 >= n) { err = "qubit out of range"; return MSV_E_ARG; }
+    if (two && (g.q1 < 0 || g.q1 >= n || g.q1 == g.q0)) { err = "bad second qubit"; return MSV_E_ARG; }
+    if ((g.kind == MSV_U1 || g.kind == MSV_U2) && !g.mat) { err = "U1/U2 gate without matrix"; return MSV_E_ARG; }
+    if (!std::isfinite(g.theta)) { err = "non-finite angle"; return MSV_E_RANGE; }
+    p = Prim();
+    p.param = g.param;
+    p.kind = (int)g.kind;
+    const double t = g.theta, c = std::cos(t / 2), s = std::sin(t / 2), h = 1.0 / std::sqrt(2.0);
+    const cd I(0.0, 1.0);
+    switch (g.kind) {
+    case MSV_H: p.q = {g.q0}; p.m = {h, h, h, -h}; break;
+    case MSV_X: p.q = {g.q0}; p.m = {0.0, 1.0, 1.0, 0.0}; break;
+    case MSV_Y: p.q = {g.q0}; p.m = {0.0, -I, I, 0.0}; break;
+    case MSV_RX: p.q = {g.q0}; p.m = {c, -I * s, -I * s, c}; break;
+    case MSV_RY: p.q = {g.q0}; p.m = {c, -s, s, c}; break;
+    case MSV_U1:
+        p.q = {g.q0};
+        p.m.resize(4);
+        for (int i = 0; i < 4; ++i) p.m[i] = cd(g.mat[2 * i], g.mat[2 * i + 1]);
+        break;
+    case MSV_Z: p.diag = true; p.q = {g.q0}; p.m = {1.0, -1.0}; break;
+    case MSV_S: p.diag = true; p.q = {g.q0}; p.m = {1.0, I}; break;
+    case MSV_T: p.diag = true; p.q = {g.q0}; p.m = {1.0, expi(kPi / 4)}; break;
+    case MSV_RZ: p.diag = true; p.q = {g.q0}; p.m = {expi(-t / 2), expi(t / 2)}; break;
+    case MSV_P: p.diag = true; p.q = {g.q0}; p.m = {1.0, expi(t)}; break;
+    case MSV_CX: p.q = {g.q1}; p.ctrl = g.q0; p.m = {0.0, 1.0, 1.0, 0.0}; break;
+    case MSV_CZ: p.diag = true; p.q = {g.q0, g.q1}; p.m = {1.0, 1.0, 1.0, -1.0}; break;
+    case MSV_CP: p.diag = true; p.q = {g.q0, g.q1}; p.m = {1.0, 1.0, 1.0, expi(t)}; break;
+    case MSV_SWAP:
+        p.q = {g.q0, g.q1};
+        p.m.assign(16, 0.0);
+        p.m[0] = p.m[1 * 4 + 2] = p.m[2 * 4 + 1] = p.m[15] = 1.0;
+        break;
+    case MSV_U2:
+        p.q = {g.q0, g.q1};
+        p.m.resize(16);
+        for (int i = 0; i < 16; ++i) p.m[i] = cd(g.mat[2 * i], g.mat[2 * i + 1]);
+        break;
+    default: err = "unknown gate kind"; return MSV_E_ARG;
+    }
+    for (const cd &v : p.m)
+        if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) { err = "non-finite matrix"; return MSV_E_RANGE; }
+    const int d = 1 << (int)p.q.size();
+    if (!p.diag && p.ctrl < 0 && is_diagonal(p.m, d)) {
+        std::vector<cd> dv(d);
+        for (int i = 0; i < d; ++i) dv[i] = p.m[i * d + i];
+        p.m = dv;
+        p.diag = true;
+    }
+    if (inverse) {
+        if (p.diag)
+            for (cd &v : p.m) v = std::conj(v);
+        else
+            p.m = dagger(p.m, d);
+    }
+    return MSV_OK;
+}
+
+namespace {
+
+// Accumulates the ops of one pass, fusing as it goes.
+struct Fuser {
+    const PlanOptions &o;
+    const std::vector<int> &local;   // tile qubits of the pass
+    std::vector<HostOp> out;
+    enum { NONE, DENSE, DIAGS } open = NONE;
+    std::vector<int> Q;
+    std::vector<cd> M;
+    std::vector<Prim> diags;          // pending diagonal prims
+
+    Fuser(const PlanOptions &opt, const std::vector<int> &loc) : o(opt), local(loc) {}
+
+    bool is_local(int q) const { return std::find(local.begin(), local.end(), q) != local.end(); }
+
+    void flush_dense()
+    {
+        HostOp op;
+        op.type = OP_DENSE;
+        op.q = Q;
+        op.m = M;
+        out.push_back(op);
+        open = NONE;
+    }
+
+    // A pending run of diagonal gates as a table over <= 5 qubits, or as a
+    // controlled linear phase; returns false when neither fits.
+    static bool diag_union(const std::vector<Prim> &ds, std::vector<int> &U)
+    {
+        U.clear();
+        for (const Prim &p : ds) U = unite(U, p.q);
+        return U.size() <= 5;
+    }
+
+    bool phase_form(const std::vector<Prim> &ds, HostOp &op) const
+    {
+        op = HostOp();
+        op.type = OP_PHASE;
+        op.mu.assign(o.n, 0.0);
+        op.lam.assign(o.n, 0.0);
+        int pend_a = -1, pend_b = -1;
+        double pend_g = 0.0;
+        for (const Prim &p : ds) {
+            if (p.q.size() == 1) {
+                op.global *= p.m[0];
+                op.mu[p.q[0]] += std::arg(p.m[1] / p.m[0]);
+                continue;
+            }
+            const int a = p.q[0], b = p.q[1];
+            const cd d0 = p.m[0], d1 = p.m[1], d2 = p.m[2], d3 = p.m[3];
+            op.global *= d0;
+            op.mu[a] += std::arg(d1 / d0);
+            op.mu[b] += std::arg(d2 / d0);
+            const double gam = std::arg(d3 * d0 / (d1 * d2));
+            if (gam == 0.0) continue;
+            if (op.hub < 0 && pend_a < 0) { pend_a = a; pend_b = b; pend_g = gam; continue; }
+            if (op.hub < 0) {
+                if (a == pend_a || a == pend_b) op.hub = a;
+                else if (b == pend_a || b == pend_b) op.hub = b;
+                else return false;
+                op.lam[op.hub == pend_a ? pend_b : pend_a] += pend_g;
+            }
+            if (a == op.hub) op.lam[b] += gam;
+            else if (b == op.hub) op.lam[a] += gam;
+            else return false;
+        }
+        if (op.hub < 0 && pend_a >= 0) {
+            op.hub = pend_b;
+            op.lam[pend_a] += pend_g;
+        }
+        return true;
+    }
+
+    bool diag_fits(const std::vector<Prim> &ds) const
+    {
+        std::vector<int> U;
+        if (diag_union(ds, U)) return true;
+        HostOp op;
+        return phase_form(ds, op);
+    }
+
+    void flush_diags()
+    {
+        std::vector<int> U;
+        if (diag_union(diags, U)) {
+            // explicit table over U
+            const int k = (int)U.size(), D = 1 << k;
+            std::vector<cd> t(D, cd(1.0));
+            for (const Prim &p : diags) {
+                std::vector<int> at;
+                for (int q : p.q) at.push_back((int)(std::find(U.begin(), U.end(), q) - U.begin()));
+                for (int s = 0; s < D; ++s) {
+                    int v = 0;
+                    for (size_t i = 0; i < at.size(); ++i) v |= ((s >> at[i]) & 1) << i;
+                    t[s] *= p.m[v];
+                }
+            }
+            HostOp op;
+            op.type = OP_DIAG;
+            op.q = U;
+            op.m = t;
+            out.push_back(op);
+        } else {
+            HostOp op;
+            phase_form(diags, op);
+            out.push_back(op);
+        }
+        diags.clear();
+        open = NONE;
+    }
+
+    void flush()
+    {
+        if (open == DENSE) flush_dense();
+        else if (open == DIAGS) flush_diags();
+    }
+
+    void add(const Prim &p)
+    {
+        if (p.diag) {
+            if (open == DENSE && subset(p.q, Q)) {
+                std::vector<cd> dm((size_t)1 << (2 * p.q.size()), cd(0.0));
+                const int d = 1 << (int)p.q.size();
+                for (int i = 0; i < d; ++i) dm[(size_t)i * d + i] = p.m[i];
+                M = matmul(embed(p.q, dm, Q), M, 1 << (int)Q.size());
+                return;
+            }
+            if (open == DIAGS) {
+                diags.push_back(p);
+                if (diag_fits(diags)) return;
+                diags.pop_back();
+                flush_diags();
+            } else {
+                flush();
+            }
+            diags.push_back(p);
+            open = DIAGS;
+            return;
+        }
+        std::vector<int> qs = p.q;
+        std::vector<cd> m = p.m;
+        if (p.ctrl >= 0) {
+            if (!is_local(p.ctrl)) {
+                flush();
+                HostOp op;
+                op.type = OP_DENSE;
+                op.q = p.q;
+                op.m = p.m;
+                op.ctrl_mask = 1ull << p.ctrl;
+                out.push_back(op);
+                return;
+            }
+            // controlled 1q U on target with local control: 4x4 on (ctrl, target)
+            qs = {p.ctrl, p.q[0]};
+            m.assign(16, 0.0);
+            m[0] = 1.0;                       // s = 0: ctrl 0, target 0
+            m[2 * 4 + 2] = 1.0;               // s = 2: ctrl 0, target 1
+            m[1 * 4 + 1] = p.m[0];            // ctrl 1: U on target bit (s = 1, 3)
+            m[1 * 4 + 3] = p.m[1];
+            m[3 * 4 + 1] = p.m[2];
+            m[3 * 4 + 3] = p.m[3];
+        }
+        if (open == DENSE) {
+            std::vector<int> U = unite(Q, qs);
+            if ((int)U.size() <= std::max(o.k_max, (int)qs.size()) && (int)U.size() <= kMaxFuse) {
+                const int D = 1 << (int)U.size();
+                M = matmul(embed(qs, m, U), embed(Q, M, U), D);
+                Q = U;
+                return;
+            }
+        }
+        flush();
+        Q = qs;
+        M = m;
+        open = DENSE;
+    }
+};
+
+}  // namespace
+
+std::vector<Pass> plan_passes(const std::vector<Prim> &prims, const PlanOptions &o)
+{
+    std::vector<Pass> passes;
+    const int tb = o.tb;
+    size_t i = 0;
+    while (i < prims.size()) {
+        std::vector<int> L = {0, 1, 2, 3, 4, 5};
+        L.resize(std::min(6, o.n));
+        size_t j = i;
+        for (; j < prims.size(); ++j) {
+            const Prim &p = prims[j];
+            if (p.diag) continue;
+            std::vector<int> U = unite(L, p.q);
+            if ((int)U.size() > tb) break;
+            L = U;
+        }
+        // fill the tile with the lowest remaining qubits
+        for (int q = 0; (int)L.size() < tb && q < o.n; ++q)
+            if (std::find(L.begin(), L.end(), q) == L.end()) L.push_back(q);
+        std::sort(L.begin(), L.end());
+        Pass ps;
+        ps.tile_q = L;
+        ps.gate_begin = prims[i].gate;
+        ps.gate_end = prims[j - 1].gate + 1;
+        Fuser f(o, ps.tile_q);
+        for (size_t k = i; k < j; ++k) f.add(prims[k]);
+        f.flush();
+        ps.ops = f.out;
+        passes.push_back(ps);
+        i = j;
+    }
+    return passes;
+}
+
+template <typename R>
+bool lower_passes(const std::vector<Pass> &passes, const PlanOptions &o, std::vector<OpDesc> &ops,
+                  std::vector<R> &pool, std::vector<PassGeom> &geoms)
+{
+    const int n = o.n, tb = o.tb, NH = 1 << (tb - 6);
+    bool ok = tb >= kMinTileBits && tb <= kMaxTileBits && tb <= n;
+    auto push = [&](cd v) {
+        pool.push_back((R)v.real());
+        pool.push_back((R)v.imag());
+    };
+    for (const Pass &ps : passes) {
+        PassGeom g{};
+        g.n = n;
+        g.tb = tb;
+        g.op_begin = (int32_t)ops.size();
+        g.n_ops = (int32_t)ps.ops.size();
+        uint64_t tmask = 0;
+        for (int i = 0; i < tb; ++i) {
+            g.tile_q[i] = ps.tile_q[i];
+            tmask |= 1ull << ps.tile_q[i];
+        }
+        const uint64_t all = n >= 64 ? ~0ull : ((1ull << n) - 1);
+        g.nontile_mask = all & ~tmask;
+        g.tile_begin = 0;
+        g.n_tiles = 1ull << (n - tb);
+        auto tpos = [&](int q) {
+            for (int i = 0; i < tb; ++i)
+                if (ps.tile_q[i] == q) return i;
+            return -1;
+        };
+        for (const HostOp &h : ps.ops) {
+            OpDesc d{};
+            d.type = h.type;
+            d.mat = (int32_t)(pool.size() / 2);
+            d.ctrl_pos = -1;
+            d.ctrl_q = -1;
+            for (int m = 0; m < 5; ++m) { d.pos[m] = -1; d.gq[m] = -1; }
+            if (h.type == OP_DENSE) {
+                d.k = (int32_t)h.q.size();
+                if (d.k >= o.mfma_min_k) d.type = OP_MFMA;
+                ok = ok && d.k >= 1 && d.k <= kMaxFuse && (int)h.m.size() == (1 << (2 * d.k));
+                for (int m = 0; m < d.k; ++m) {
+                    d.pos[m] = tpos(h.q[m]);
+                    ok = ok && d.pos[m] >= 0;
+                }
+                ok = ok && (h.ctrl_mask & tmask) == 0;
+                d.ctrl_fixed = h.ctrl_mask;
+                for (const cd &v : h.m) push(v);
+            } else if (h.type == OP_DIAG) {
+                d.k = (int32_t)h.q.size();
+                ok = ok && d.k >= 1 && d.k <= 5 && (int)h.m.size() == (1 << d.k);
+                for (int m = 0; m < d.k; ++m) {
+                    d.gq[m] = h.q[m];
+                    d.pos[m] = tpos(h.q[m]);
+                }
+                for (const cd &v : h.m) push(v);
+            } else {
+                d.k = 0;
+                d.ctrl_q = h.hub;
+                d.ctrl_pos = h.hub >= 0 ? tpos(h.hub) : -1;
+                d.ctrl_fixed = g.nontile_mask;
+                // loA (with the global factor), hiA, loB, hiB, fixA[n], fixB[n]
+                for (int a = 0; a < 64; ++a) {
+                    double ph = 0.0;
+                    for (int i = 0; i < 6; ++i)
+                        if ((a >> i) & 1) ph += h.mu[ps.tile_q[i]];
+                    push(h.global * expi(ph));
+                }
+                for (int a = 0; a < NH; ++a) {
+                    double ph = 0.0;
+                    for (int i = 0; i < tb - 6; ++i)
+                        if ((a >> i) & 1) ph += h.mu[ps.tile_q[6 + i]];
+                    push(expi(ph));
+                }
+                for (int a = 0; a < 64; ++a) {
+                    double ph = 0.0;
+                    for (int i = 0; i < 6; ++i)
+                        if ((a >> i) & 1) ph += h.lam[ps.tile_q[i]];
+                    push(expi(ph));
+                }
+                for (int a = 0; a < NH; ++a) {
+                    double ph = 0.0;
+                    for (int i = 0; i < tb - 6; ++i)
+                        if ((a >> i) & 1) ph += h.lam[ps.tile_q[6 + i]];
+                    push(expi(ph));
+                }
+                for (int q = 0; q < n; ++q) push((g.nontile_mask >> q) & 1 ? expi(h.mu[q]) : cd(1.0));
+                for (int q = 0; q < n; ++q) push((g.nontile_mask >> q) & 1 ? expi(h.lam[q]) : cd(1.0));
+            }
+            ops.push_back(d);
+        }
+        ok = ok && (int)ps.tile_q.size() == tb && ps.tile_q[0] == 0 && ps.tile_q[5] == 5;
+        geoms.push_back(g);
+    }
+    return ok;
+}
+
+template bool lower_passes<float>(const std::vector<Pass> &, const PlanOptions &, std::vector<OpDesc> &,
+                                  std::vector<float> &, std::vector<PassGeom> &);
+template bool lower_passes<double>(const std::vector<Pass> &, const PlanOptions &, std::vector<OpDesc> &,
+                                   std::vector<double> &, std::vector<PassGeom> &);
+
+}  // namespace msv

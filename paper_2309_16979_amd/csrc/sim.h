@@ -1,0 +1,78 @@
+// Host-side state of one simulator handle.
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/msv.h"
+#include "kernels.h"
+#include "planner.h"
+
+namespace msv {
+
+// Device memory block from the caller's allocator or hipMalloc.
+struct DevMem {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+// Pinned host memory block (hipHostMalloc).
+struct HostMem {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+// Compressed blocks of the whole state, resident in HBM (device store).
+struct DevStore {
+    DevMem W, A, OFF, heap;
+    BlockStore view() const
+    {
+        return BlockStore{(uint8_t *)W.p, (int32_t *)A.p, (uint32_t *)OFF.p, (uint64_t *)heap.p, nullptr, 0};
+    }
+};
+
+// Compressed chunks in pinned host memory (host store): one arena per side of
+// the ping-pong, each chunk at chunk_off[c] with chunk_bytes[c] bytes.
+struct HostStore {
+    HostMem arena[2];
+    std::vector<uint64_t> off[2], bytes[2];
+    int cur = 0;
+};
+
+struct Workspace {
+    DevMem ops, pool, part, pass_off, pass_stats, flags, red, red_out, masks, tmp, tmp2;
+    HostMem pin;       // small pinned staging for descriptors and results
+};
+
+}  // namespace msv
+
+struct msv_sim {
+    int n = 0, dtype = MSV_C64, log2c = 20, store = MSV_STORE_DEVICE;
+    double eb = 0.0;
+    int k_max = 2, mma = MSV_MMA_F32, tile_bits = 0, renorm = 0, check_bound = 1, mfma_min_k = 6;
+    int batch_chunks = 0;
+    void *(*alloc)(size_t, void *) = nullptr;
+    void (*dealloc)(void *, void *) = nullptr;
+    void *actx = nullptr;
+    hipStream_t user_stream = nullptr, own_stream = nullptr, copy_stream = nullptr;
+    bool inited = false, poisoned = false;
+    std::string err;
+
+    msv::DevMem amps;          // uncompressed state (eb = 0)
+    msv::DevStore st[2];       // device store ping-pong
+    int cur = 0;
+    msv::HostStore hs;         // host store
+    msv::Workspace ws;
+    double scale = 1.0;        // pending renormalisation factor, applied at decode
+    msv_stats stats{};
+    double max_err_all = 0.0;
+    uint64_t compressed_words = 0;  // payload words of the current state
+
+    hipStream_t stream() const { return user_stream ? user_stream : own_stream; }
+    bool is_double() const { return dtype == MSV_C128; }
+    size_t elt() const { return dtype == MSV_C128 ? 16 : 8; }
+    bool compressed() const { return eb > 0.0; }
+    double inv_step() const { return 1.0 / (2.0 * eb); }
+    double step() const { return 2.0 * eb; }
+};

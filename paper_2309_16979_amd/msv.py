@@ -1,0 +1,214 @@
+"""Python binding of the compressed state-vector simulator (libmsv).
+
+Argument marshalling only: every step runs in the HIP kernels behind the C ABI.
+PyTorch supplies device memory (its caching allocator, through the ABI's
+allocator hook) and the HIP stream (its current stream).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import MsvError, check, load
+
+_DT = {"c128": L.C128, "complex128": L.C128, "c64": L.C64, "complex64": L.C64}
+_MMA = {"f64": L.MMA_F64, "f32": L.MMA_F32, "bf16": L.MMA_BF16}
+_STORE = {"device": L.STORE_DEVICE, "host": L.STORE_HOST_PINNED}
+
+
+def gate_array(gates: Sequence):
+    """Marshal gate records (name, q0, q1, theta, param, mat) into msv_gate[]."""
+    arr = (L.Gate * max(1, len(gates)))()
+    keep = []
+    for i, g in enumerate(gates):
+        m = None
+        if getattr(g, "mat", None) is not None:
+            v = np.asarray(g.mat, dtype=np.complex128).ravel()
+            buf = np.ascontiguousarray(np.stack([v.real, v.imag], axis=1).ravel())
+            keep.append(buf)
+            m = buf.ctypes.data_as(C.POINTER(C.c_double))
+        arr[i] = L.Gate(L.KINDS[g.name], int(g.q0), int(g.q1), float(g.theta),
+                        int(getattr(g, "param", -1)), m)
+    return arr, keep
+
+
+class _TorchMemory:
+    """Device memory and stream from PyTorch for one simulator handle."""
+
+    def __init__(self):
+        import torch
+        self.torch = torch
+        self.blocks = {}
+        self.alloc_cb = L.ALLOC_FN(self._alloc)
+        self.free_cb = L.FREE_FN(self._free)
+
+    def _alloc(self, nbytes, ctx):
+        try:
+            t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device="cuda")
+        except Exception:
+            return None
+        p = t.data_ptr()
+        self.blocks[p] = t
+        return p
+
+    def _free(self, ptr, ctx):
+        self.blocks.pop(ptr, None)
+
+    def stream_handle(self):
+        return self.torch.cuda.current_stream().cuda_stream
+
+
+class Simulator:
+    """An n-qubit state held as compressed chunks (eb > 0) or plain amplitudes.
+
+    Parameters mirror the setters of the C ABI: dtype "c128"/"c64", eb the
+    absolute error bound per component (0 = uncompressed), chunk_qubits,
+    store "device"/"host", k_max fusion width, mma "f64"/"f32"/"bf16",
+    options a dict for msv_set_option. use_torch routes device memory and the
+    stream through PyTorch (default when a GPU is visible to torch).
+    """
+
+    def __init__(self, n: int, dtype: str = "c64", eb: float = 0.0,
+                 chunk_qubits: Optional[int] = None, store: str = "device", k_max: int = 2,
+                 mma: Optional[str] = None, options: Optional[dict] = None,
+                 use_torch: Optional[bool] = None):
+        self._L = load()
+        self.n = n
+        self.dtype = _DT[dtype]
+        self.np_dtype = np.complex128 if self.dtype == L.C128 else np.complex64
+        h = C.c_void_p()
+        check(self._L.msv_create(n, self.dtype, C.byref(h)))
+        self.h = h
+        self._mem = None
+        try:
+            if chunk_qubits is not None:
+                check(self._L.msv_set_chunk_qubits(h, chunk_qubits), h)
+            check(self._L.msv_set_error_bound(h, float(eb)), h)
+            check(self._L.msv_set_store(h, _STORE[store]), h)
+            if mma is None:
+                mma = "f64" if self.dtype == L.C128 else "f32"
+            check(self._L.msv_set_fusion(h, k_max, _MMA[mma]), h)
+            for k, v in (options or {}).items():
+                check(self._L.msv_set_option(h, k.encode(), float(v)), h)
+            if use_torch is None:
+                try:
+                    import torch
+                    use_torch = bool(torch.cuda.is_available())
+                except ImportError:
+                    use_torch = False
+            if use_torch:
+                self._mem = _TorchMemory()
+                check(self._L.msv_set_device_allocator(h, self._mem.alloc_cb, self._mem.free_cb, None), h)
+                check(self._L.msv_set_stream(h, self._mem.stream_handle()), h)
+        except Exception:
+            self.close()
+            raise
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.msv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _chk(self, code):
+        return check(code, self.h)
+
+    # -- state
+    def init_basis(self, index: int = 0):
+        self._chk(self._L.msv_init_basis(self.h, int(index)))
+
+    def init_state(self, amps: np.ndarray):
+        a = np.ascontiguousarray(amps, dtype=self.np_dtype)
+        if a.size != 1 << self.n:
+            raise ValueError("state must have 2^n amplitudes")
+        self._chk(self._L.msv_init_state(self.h, a.ctypes.data))
+
+    def apply(self, gates: Sequence):
+        arr, keep = gate_array(gates)
+        self._chk(self._L.msv_apply(self.h, arr, len(gates)))
+        del keep
+
+    # -- measurement
+    def prob_one(self, qubit: int) -> float:
+        out = C.c_double()
+        self._chk(self._L.msv_prob_one(self.h, qubit, C.byref(out)))
+        return out.value
+
+    def expect_z(self, masks: Iterable[int], coeffs: Iterable[float]) -> float:
+        m = np.ascontiguousarray(list(masks), dtype=np.uint64)
+        c = np.ascontiguousarray(list(coeffs), dtype=np.float64)
+        out = C.c_double()
+        self._chk(self._L.msv_expect_z(self.h, m.ctypes.data, c.ctypes.data, len(m), C.byref(out)))
+        return out.value
+
+    def amplitudes(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
+        if count is None:
+            count = (1 << self.n) - first
+        out = np.empty(count, dtype=self.np_dtype)
+        self._chk(self._L.msv_get_amplitudes(self.h, first, count, out.ctypes.data))
+        return out
+
+    def fidelity(self, ref: np.ndarray):
+        r = np.ascontiguousarray(ref, dtype=np.complex128)
+        fr, fn = C.c_double(), C.c_double()
+        code = self._L.msv_fidelity(self.h, r.ctypes.data, C.byref(fr), C.byref(fn))
+        if code not in (L.OK, L.E_NORM):
+            self._chk(code)
+        return fr.value, (fn.value if code == L.OK else float("nan"))
+
+    def stats(self) -> dict:
+        st = L.Stats()
+        self._chk(self._L.msv_get_stats(self.h, C.byref(st)))
+        return st.as_dict()
+
+    def export_chunk(self, chunk: int) -> bytes:
+        need = C.c_size_t(0)
+        code = self._L.msv_export_chunk(self.h, chunk, None, 0, C.byref(need))
+        if code not in (L.OK, L.E_ARG) or need.value == 0:
+            self._chk(code)
+        buf = np.zeros(need.value, dtype=np.uint8)
+        self._chk(self._L.msv_export_chunk(self.h, chunk, buf.ctypes.data, need.value, C.byref(need)))
+        return buf[: need.value].tobytes()
+
+
+def codec_bound(log2c: int) -> int:
+    return int(load().msv_codec_bound(log2c))
+
+
+def codec_encode(values: np.ndarray, log2c: int, eb: float) -> bytes:
+    """Encode one chunk on the GPU (format MSVC v1)."""
+    v = np.ascontiguousarray(values)
+    dt = {np.dtype(np.complex128): L.C128, np.dtype(np.complex64): L.C64}[v.dtype]
+    if v.size != 1 << log2c:
+        raise ValueError("chunk must hold 2^log2c values")
+    cap = codec_bound(log2c)
+    out = np.zeros(cap, dtype=np.uint8)
+    n = C.c_size_t(0)
+    check(load().msv_codec_encode(dt, log2c, float(eb), v.ctypes.data, out.ctypes.data, cap, C.byref(n)))
+    return out[: n.value].tobytes()
+
+
+def codec_decode(blob: bytes, dtype: str = "c64") -> np.ndarray:
+    b = np.frombuffer(blob, dtype=np.uint8)
+    if len(blob) < 32:
+        raise MsvError(L.E_ARG, "chunk shorter than its header")
+    log2c = blob[6]
+    out = np.zeros(1 << log2c, dtype=np.complex128 if _DT[dtype] == L.C128 else np.complex64)
+    check(load().msv_codec_decode(_DT[dtype], b.ctypes.data, len(blob), out.ctypes.data))
+    return out
