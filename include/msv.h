@@ -92,6 +92,12 @@ typedef struct msv_stats {
     double overlap;              /* fraction of copy time hidden under kernels    */
     uint64_t bound_violations;   /* passes whose max error exceeded err_bound     */
     uint64_t kernel_launches;    /* kernels launched by the last apply            */
+    double t_pass;               /* seconds inside pass kernels (events around each
+                                    pass launch; option "time_passes")            */
+    uint64_t pass_bytes;         /* algorithmic bytes of the pass kernels of the
+                                    last apply: per pass, compressed blocks read and
+                                    written (payload + 9 bytes of W/A/OFF per block)
+                                    or 2 x 2^n x sizeof(complex) uncompressed      */
 } msv_stats;
 
 typedef struct msv_sim msv_sim;  /* opaque, library-owned */
@@ -128,7 +134,8 @@ int msv_set_fusion(msv_sim *sim, int k_max, int mma_precision);
  *   "renormalize"  1 = rescale to unit norm at the next decode after each pass
  *   "check_bound"  1 (default) = FP64 max |x - x'| per pass
  *   "mfma_min_k"   smallest fused width run on matrix cores (3..6; 6 = never)
- *   "batch_chunks" host store: chunks per streamed batch (0 = automatic) */
+ *   "batch_chunks" host store: chunks per streamed batch (0 = automatic)
+ *   "time_passes"  1 = time every pass kernel with events (msv_stats.t_pass) */
 int msv_set_option(msv_sim *sim, const char *key, double value);
 /* Device memory provider (e.g. a framework's caching allocator). alloc returns
  * NULL on failure; both are called on the calling thread. Without it the

@@ -9,7 +9,7 @@
 #include <cstring>
 #include <new>
 
-#include "sim.h"
+#include "internal.h"
 
 using namespace msv;
 
@@ -34,6 +34,7 @@ int fail(msv_sim *s, int code, const char *fmt, ...)
 namespace msv {
 
 int fail_global(int code, const char *msg) { return fail(nullptr, code, "%s", msg); }
+int fail_sim(msv_sim *s, int code, const char *msg) { return fail(s, code, "%s", msg); }
 
 int hip_fail(msv_sim *s, hipError_t e, const char *what)
 {
@@ -41,12 +42,6 @@ int hip_fail(msv_sim *s, hipError_t e, const char *what)
     if (s) s->poisoned = true;
     return fail(s, MSV_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
-
-#define HIPCHK(s, expr)                                                 \
-    do {                                                                \
-        hipError_t e_ = (expr);                                         \
-        if (e_ != hipSuccess) return msv::hip_fail((s), e_, #expr);     \
-    } while (0)
 
 int dev_free(msv_sim *s, DevMem &m)
 {
@@ -156,13 +151,6 @@ int alloc_device_store(msv_sim *s)
     return MSV_OK;
 }
 
-int apply_host_store(msv_sim *s, const std::vector<Prim> &prims, size_t n_gates);
-int init_host_store_basis(msv_sim *s, uint64_t index);
-int init_host_store_state(msv_sim *s, const void *host);
-int host_store_decode_range(msv_sim *s, uint64_t first_amp, uint64_t count, void *dev_out);
-int host_store_reduce(msv_sim *s, ReduceArgs a, double *out4);
-void host_store_free(msv_sim *s);
-
 // Runs a list of passes over the device-resident state (plain or compressed).
 int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOptions &o, double *norm_last,
                       double *err_last, double *words_last, std::vector<double> *per_pass)
@@ -207,6 +195,15 @@ int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOpt
     HIPCHK(s, hipMemsetAsync(s->ws.flags.p, 0, 4, stream));
     double *part = (double *)s->ws.part.p;
     double *pstats = (double *)s->ws.pass_stats.p;
+    std::vector<hipEvent_t> ev;
+    if (s->time_passes) {
+        ev.resize(2 * n_passes, nullptr);
+        for (auto &e : ev) HIPCHK(s, hipEventCreate(&e));
+    }
+    struct EvGuard {
+        std::vector<hipEvent_t> &v;
+        ~EvGuard() { for (auto e : v) if (e) (void)hipEventDestroy(e); }
+    } evg{ev};
     for (size_t p = 0; p < n_passes; ++p) {
         PassBuffers b{};
         b.amps_in = b.amps_out = s->amps.p;
@@ -228,7 +225,9 @@ int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOpt
         if (!c && p == 0 && s->scale != 1.0) {
             // plain state: a pending scale is applied by a no-op pass first
         }
+        if (s->time_passes) HIPCHK(s, hipEventRecord(ev[2 * p], stream));
         HIPCHK(s, launch_pass(s->is_double(), c, c, geoms[p], b, stream));
+        if (s->time_passes) HIPCHK(s, hipEventRecord(ev[2 * p + 1], stream));
         if (s->renorm)
             HIPCHK(s, launch_pass_stats(part + 3 * offs[p], (const uint64_t *)s->ws.pass_off.p + p, 1,
                                         pstats + 3 * p, stream));
@@ -244,6 +243,27 @@ int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOpt
     HIPCHK(s, hipMemcpyAsync(hflags, s->ws.flags.p, 4, hipMemcpyDeviceToHost, stream));
     HIPCHK(s, hipStreamSynchronize(stream));
     if (per_pass) per_pass->assign(hout, hout + 3 * n_passes);
+    s->stats.t_pass = 0.0;
+    for (size_t p = 0; p < ev.size() / 2; ++p) {
+        float ms = 0.f;
+        HIPCHK(s, hipEventElapsedTime(&ms, ev[2 * p], ev[2 * p + 1]));
+        s->stats.t_pass += ms * 1e-3;
+    }
+    {
+        // algorithmic bytes of the pass kernels
+        const uint64_t nblk = 2ull << (s->n - 6);
+        uint64_t bytes = 0;
+        double words_in = (double)s->compressed_words;
+        for (size_t p = 0; p < n_passes; ++p) {
+            if (s->compressed()) {
+                bytes += 18 * nblk + (uint64_t)(8.0 * (words_in + hout[3 * p + 2]));
+                words_in = hout[3 * p + 2];
+            } else {
+                bytes += 2 * ((uint64_t)s->elt() << s->n);
+            }
+        }
+        s->stats.pass_bytes = bytes;
+    }
     if (n_passes) {
         *norm_last = hout[3 * (n_passes - 1)];
         *err_last = hout[3 * (n_passes - 1) + 1];
@@ -382,6 +402,8 @@ int msv_set_option(msv_sim *s, const char *key, double v)
     } else if (!strcmp(key, "mfma_min_k")) {
         if (v != iv || iv < 3 || iv > 6) return fail(s, MSV_E_ARG, "mfma_min_k in 3..6");
         s->mfma_min_k = iv;
+    } else if (!strcmp(key, "time_passes")) {
+        s->time_passes = v != 0.0;
     } else if (!strcmp(key, "batch_chunks")) {
         if (v != iv || iv < 0) return fail(s, MSV_E_ARG, "batch_chunks >= 0");
         s->batch_chunks = iv;
@@ -585,17 +607,22 @@ int msv_apply(msv_sim *s, const msv_gate *gates, size_t n_gates)
 // Reduction over the whole state; out4 = {sum |psi|^2, q1, q2, q3}.
 static int reduce_state(msv_sim *s, ReduceArgs a, double *out4)
 {
-    if (s->store == MSV_STORE_HOST_PINNED) return host_store_reduce(s, a, out4);
     hipStream_t stream = s->stream();
     int st;
-    if ((st = dev_alloc(s, s->ws.red, 4 * 8 * 2048))) return st;
+    const uint64_t max_groups = s->store == MSV_STORE_HOST_PINNED
+                                    ? 2048 * ((1ull << (s->n - s->log2c)) + 1) : 2048;
+    if ((st = dev_alloc(s, s->ws.red, 4 * 8 * max_groups))) return st;
     if ((st = dev_alloc(s, s->ws.red_out, 256))) return st;
     a.partials = (double *)s->ws.red.p;
     a.scale = s->scale;
     if (!a.amp_count) { a.amp_begin = 0; a.amp_count = 1ull << s->n; }
     int groups = 0;
-    HIPCHK(s, launch_reduce(s->is_double(), s->compressed(), s->amps.p, s->st[s->cur].view(),
-                            s->compressed() ? s->step() : 0.0, a, &groups, stream));
+    if (s->store == MSV_STORE_HOST_PINNED) {
+        if ((st = host_store_reduce(s, a, &groups))) return st;
+    } else {
+        HIPCHK(s, launch_reduce(s->is_double(), s->compressed(), s->amps.p, s->st[s->cur].view(),
+                                s->compressed() ? s->step() : 0.0, a, &groups, stream));
+    }
     HIPCHK(s, launch_reduce_final(a.partials, groups, (double *)s->ws.red_out.p, stream));
     HIPCHK(s, hipMemcpyAsync(out4, s->ws.red_out.p, 32, hipMemcpyDeviceToHost, stream));
     HIPCHK(s, hipStreamSynchronize(stream));
@@ -688,7 +715,9 @@ int msv_fidelity(msv_sim *s, const double *ref, double *f_raw, double *f_norm)
     int st;
     if ((st = dev_alloc(s, s->ws.tmp2, 16 * piece))) return st;
     const uint64_t n_pieces = N / piece;
-    if ((st = dev_alloc(s, s->ws.red, 4 * 8 * 2048 * n_pieces))) return st;
+    const uint64_t per_piece = s->store == MSV_STORE_HOST_PINNED
+                                   ? 2048 * ((piece >> s->log2c) + 1) : 2048;
+    if ((st = dev_alloc(s, s->ws.red, 4 * 8 * per_piece * n_pieces))) return st;
     if ((st = dev_alloc(s, s->ws.red_out, 256))) return st;
     int total_groups = 0;
     for (uint64_t p = 0; p < n_pieces; ++p) {
@@ -702,12 +731,11 @@ int msv_fidelity(msv_sim *s, const double *ref, double *f_raw, double *f_norm)
         a.scale = s->scale;
         int groups = 0;
         if (s->store == MSV_STORE_HOST_PINNED) {
-            double o4[4];
-            if ((st = host_store_reduce(s, a, o4))) return st;
-            return fail(s, MSV_E_UNSUPPORTED, "fidelity on the host store");
+            if ((st = host_store_reduce(s, a, &groups))) return st;
+        } else {
+            HIPCHK(s, launch_reduce(s->is_double(), s->compressed(), s->amps.p, s->st[s->cur].view(),
+                                    s->compressed() ? s->step() : 0.0, a, &groups, stream));
         }
-        HIPCHK(s, launch_reduce(s->is_double(), s->compressed(), s->amps.p, s->st[s->cur].view(),
-                                s->compressed() ? s->step() : 0.0, a, &groups, stream));
         total_groups += groups;
         // the next piece's copy must not overwrite ref data still being read
         HIPCHK(s, hipStreamSynchronize(stream));
@@ -743,7 +771,7 @@ int msv_get_stats(msv_sim *s, msv_stats *out)
             uint64_t tot = 0;
             for (uint64_t b : s->hs.bytes[s->hs.cur]) tot += b;
             r.compressed_bytes = tot;
-            r.reserved_bytes = s->hs.arena[0].bytes + s->hs.arena[1].bytes;
+            r.reserved_bytes = s->hs.arena[0].reserved() + s->hs.arena[1].reserved();
         }
         r.ratio = r.compressed_bytes ? (double)r.uncompressed_bytes / (double)r.compressed_bytes : 0.0;
     } else {

@@ -74,7 +74,8 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, Bloc
     using V2 = typename Vec2<T>::V;
     constexpr int NW = kThreads / 64;
     __shared__ double sacc[4][NW];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t nab = a.amp_count >> 6, first = a.amp_begin >> 6;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (uint64_t k = (uint64_t)blockIdx.x * NW + wave; k < nab; k += (uint64_t)gridDim.x * NW) {
@@ -208,7 +209,8 @@ __global__ __launch_bounds__(kThreads) void decode_range_kernel(BlockStore st, d
 {
     using V2 = typename Vec2<T>::V;
     constexpr int NW = kThreads / 64;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (uint64_t k = (uint64_t)blockIdx.x * NW + wave; k < nab; k += (uint64_t)gridDim.x * NW) {
         const uint64_t G = first + k;
         V2 v;
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(kThreads) void encode_chunks_kernel(const T *vals, 
 {
     constexpr int NW = kThreads / 64;
     const uint32_t lane = lane_id();
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     double err = 0.0;
     bool bad = false;
     for (uint64_t b = (uint64_t)blockIdx.x * NW + wave; b < n_blocks; b += (uint64_t)gridDim.x * NW) {
@@ -379,7 +381,7 @@ __global__ __launch_bounds__(kThreads) void assemble_chunks_kernel(int dtype, in
 {
     constexpr int NW = kThreads / 64;
     const uint32_t lane = lane_id();
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t total_blocks = nb * n_chunks;
     const uint64_t a_off = 32 + pad8(nb), p_off = a_off + pad8(4 * nb);
     for (uint64_t gb = (uint64_t)blockIdx.x * NW + wave; gb < total_blocks; gb += (uint64_t)gridDim.x * NW) {

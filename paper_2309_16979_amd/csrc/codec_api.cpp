@@ -7,14 +7,9 @@
 #include <cstring>
 #include <string>
 
-#include "sim.h"
+#include "internal.h"
 
 using namespace msv;
-
-namespace msv {
-int hip_fail(msv_sim *s, hipError_t e, const char *what);
-int fail_global(int code, const char *msg);
-}
 
 namespace {
 
@@ -148,10 +143,11 @@ int msv_export_chunk(msv_sim *s, uint64_t chunk, void *host_out, size_t cap, siz
     const uint64_t n_chunks = 1ull << (s->n - s->log2c);
     if (chunk >= n_chunks) return cfail(MSV_E_ARG, "chunk index out of range");
     if (s->store == MSV_STORE_HOST_PINNED) {
-        const uint64_t bytes = s->hs.bytes[s->hs.cur][chunk];
+        const int c = s->hs.cur;
+        const uint64_t bytes = s->hs.bytes[c][chunk];
         *out_bytes = bytes;
         if (!host_out || cap < bytes) return cfail(MSV_E_ARG, "output buffer too small");
-        memcpy(host_out, (const uint8_t *)s->hs.arena[s->hs.cur].p + s->hs.off[s->hs.cur][chunk], bytes);
+        memcpy(host_out, s->hs.arena[c].at(s->hs.pos[c][chunk]), bytes);
         return MSV_OK;
     }
     const uint64_t nb = (2ull << s->log2c) / 64, b0 = chunk * nb;

@@ -66,10 +66,14 @@ __device__ __forceinline__ T dequantize(int32_t q, double step)
     return (T)((double)q * step);
 }
 
-// Zigzag of the Lorenzo-1 residual d_i = q_i - q_(i-1), d_0 = 0.
+// Zigzag of the Lorenzo-1 residual d_i = q_i - q_(i-1), d_0 = 0. The shifted
+// copy stays a separate v_mov_dpp (the empty asm hides it from the DPP
+// combiner), so the subtraction is an ordinary VALU op whose operand order is
+// explicit.
 __device__ __forceinline__ uint32_t residual_zigzag(int32_t q)
 {
-    const uint32_t prev = wave_shift_up1((uint32_t)q);
+    uint32_t prev = wave_shift_up1((uint32_t)q);
+    asm volatile("" : "+v"(prev));
     const int32_t d = lane_id() == 0 ? 0 : (int32_t)((uint32_t)q - prev);
     return ((uint32_t)d << 1) ^ (uint32_t)(d >> 31);
 }

@@ -1,0 +1,34 @@
+// Helpers shared by the host-side translation units of the library.
+#pragma once
+#include "sim.h"
+
+namespace msv {
+
+int fail_global(int code, const char *msg);
+int fail_sim(msv_sim *s, int code, const char *msg);
+int hip_fail(msv_sim *s, hipError_t e, const char *what);
+int dev_alloc(msv_sim *s, DevMem &m, size_t bytes);
+int dev_free(msv_sim *s, DevMem &m);
+int host_alloc(msv_sim *s, HostMem &m, size_t bytes);
+void host_free(HostMem &m);
+int ensure_stream(msv_sim *s);
+int choose_tile_bits(const msv_sim *s);
+double bound_for(const msv_sim *s, double norm2);
+
+// Host store (compressed chunks in pinned host memory).
+int apply_host_store(msv_sim *s, const std::vector<Prim> &prims, size_t n_gates);
+int init_host_store_basis(msv_sim *s, uint64_t index);
+int init_host_store_state(msv_sim *s, const void *host);
+int host_store_decode_range(msv_sim *s, uint64_t first_amp, uint64_t count, void *dev_out);
+// Per-workgroup partials of a reduction over [a.amp_begin, a.amp_begin +
+// a.amp_count), written from a.partials on; *groups receives their count.
+int host_store_reduce(msv_sim *s, ReduceArgs a, int *groups);
+void host_store_free(msv_sim *s);
+
+}  // namespace msv
+
+#define HIPCHK(s, expr)                                                 \
+    do {                                                                \
+        hipError_t e_ = (expr);                                         \
+        if (e_ != hipSuccess) return msv::hip_fail((s), e_, #expr);     \
+    } while (0)

@@ -192,7 +192,8 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassGeom geo, PassBuffer
     __shared__ double sred[2 * NW];
     __shared__ T sph[2 * (128 + (1 << (TB - 6)))];
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform for the compiler
     const uint64_t tile = geo.tile_begin + blockIdx.x;
 
     // global index of the tile's amplitude 0: tile bits deposited into the

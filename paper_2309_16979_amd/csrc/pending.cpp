@@ -3,20 +3,7 @@
 
 namespace msv {
 int fail_global(int code, const char *msg);
-
-int apply_host_store(msv_sim *, const std::vector<Prim> &, size_t)
-{
-    return fail_global(MSV_E_UNSUPPORTED, "host store not available");
 }
-int init_host_store_basis(msv_sim *, uint64_t) { return fail_global(MSV_E_UNSUPPORTED, "host store not available"); }
-int init_host_store_state(msv_sim *, const void *) { return fail_global(MSV_E_UNSUPPORTED, "host store not available"); }
-int host_store_decode_range(msv_sim *, uint64_t, uint64_t, void *)
-{
-    return fail_global(MSV_E_UNSUPPORTED, "host store not available");
-}
-int host_store_reduce(msv_sim *, ReduceArgs, double *) { return fail_global(MSV_E_UNSUPPORTED, "host store not available"); }
-void host_store_free(msv_sim *) {}
-}  // namespace msv
 
 extern "C" {
 int msv_adjoint(msv_sim *, const msv_gate *, size_t, const double *, size_t, const uint64_t *, const double *, size_t,

@@ -32,12 +32,37 @@ struct DevStore {
     }
 };
 
-// Compressed chunks in pinned host memory (host store): one arena per side of
-// the ping-pong, each chunk at chunk_off[c] with chunk_bytes[c] bytes.
+// Pinned host memory for compressed chunks: fixed-size segments, written
+// front to back; position p lives in segment p / seg_bytes.
+struct HostArena {
+    std::vector<HostMem> segs;
+    size_t seg_bytes = 0;
+    size_t seg = 0, off = 0;   // write cursor
+    uint8_t *at(uint64_t pos) const { return (uint8_t *)segs[pos / seg_bytes].p + pos % seg_bytes; }
+    size_t reserved() const { return segs.size() * seg_bytes; }
+};
+
+// Device buffers and events of one in-flight batch of chunk groups.
+struct BatchBufs {
+    DevMem in_stage, in_W, in_A, in_OFF, out_W, out_A, out_OFF, out_heap, out_stage, dst_off, meta;
+    HostMem pin_in, pin_meta;
+    hipEvent_t h2d_beg = nullptr, h2d_done = nullptr, k_beg = nullptr, k_done = nullptr,
+               d2h_beg = nullptr, d2h_done = nullptr;
+    bool h2d_used = false, d2h_used = false;
+};
+
+// Compressed chunks in pinned host memory (host store): two arenas (the pass
+// reads one and writes the other); chunk c of side s is at pos[s][c] with
+// bytes[s][c] bytes (canonical format).
 struct HostStore {
-    HostMem arena[2];
-    std::vector<uint64_t> off[2], bytes[2];
+    HostArena arena[2];
+    std::vector<uint64_t> pos[2], bytes[2];
     int cur = 0;
+    BatchBufs bb[2];
+    DevMem zero_blob, part, plain;
+    hipStream_t h2d = nullptr, d2h = nullptr;
+    uint64_t cap_chunks = 0;   // chunks per batch buffer
+    bool ready = false;
 };
 
 struct Workspace {
@@ -52,6 +77,7 @@ struct msv_sim {
     double eb = 0.0;
     int k_max = 2, mma = MSV_MMA_F32, tile_bits = 0, renorm = 0, check_bound = 1, mfma_min_k = 6;
     int batch_chunks = 0;
+    int time_passes = 0;
     void *(*alloc)(size_t, void *) = nullptr;
     void (*dealloc)(void *, void *) = nullptr;
     void *actx = nullptr;

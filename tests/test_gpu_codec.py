@@ -92,3 +92,16 @@ def test_rejections():
     with pytest.raises(MsvError) as e:
         codec_decode(bytes(blob[:-8]), "c128")
     assert e.value.code == -6
+
+
+@pytest.mark.parametrize("dtype", [np.complex128, np.complex64])
+@pytest.mark.parametrize("lc,sigma,eb", [(6, 1e-3, 1e-5), (12, 2 ** -14.5, 1e-5), (16, 1e-2, 1e-4)])
+def test_decode_of_oracle_chunks_bit_exact(dtype, lc, sigma, eb):
+    from paper_2309_16979_amd import codec_decode
+    x = _gauss(lc, sigma, dtype, seed=lc + 1)
+    blob = oracle.codec_encode(x, lc, eb)
+    log("codec decode", dtype.__name__, lc, sigma, eb)
+    dt = "c128" if dtype == np.complex128 else "c64"
+    got = codec_decode(blob, dt)
+    ref = oracle.codec_decode(blob)
+    assert np.array_equal(got.view(np.uint8), ref.view(np.uint8))

@@ -101,3 +101,47 @@ def test_qft_workload_small_collapses_as_expected():
         fr, fn = s.fidelity(oracle.simulate(n, gates, x))
     assert st["bound_violations"] == 0
     assert fr < 1e-6 and math.isnan(fn) or fn >= 0
+
+
+@pytest.mark.parametrize("dtype,n,lc,eb,batch", [("c64", 16, 10, 1e-5, 0), ("c64", 18, 12, 1e-5, 16),
+                                                 ("c128", 16, 8, 1e-6, 0)])
+def test_host_store_matches_device_store_bitwise(dtype, n, lc, eb, batch):
+    """Chunks streamed from pinned host memory through the same pass kernels give
+    exactly the device store's codes: identical amplitudes and chunk bytes."""
+    gates = random_circuit(n, 12, seed=5)
+    ref = oracle.simulate(n, gates, 1)
+    out = {}
+    for store in ("device", "host"):
+        log("store", store, dtype, n, lc, eb)
+        opts = {"batch_chunks": batch} if store == "host" else {}
+        with _sim(n, dtype, eb, chunk_qubits=lc, store=store, options=opts) as s:
+            s.init_basis(1)
+            s.apply(gates)
+            st = s.stats()
+            out[store] = (s.amplitudes(), [s.export_chunk(c) for c in range(0, 1 << (n - lc), 7)],
+                          s.fidelity(ref), s.prob_one(n - 1), st)
+    a_dev, ch_dev, f_dev, p_dev, st_dev = out["device"]
+    a_host, ch_host, f_host, p_host, st_host = out["host"]
+    assert np.array_equal(a_dev.view(np.uint8), a_host.view(np.uint8))
+    assert ch_dev == ch_host
+    assert f_dev == pytest.approx(f_host, rel=1e-12) and p_dev == pytest.approx(p_host, rel=1e-12)
+    assert st_host["bound_violations"] == 0 and st_host["passes"] == st_dev["passes"]
+    assert st_host["h2d_bytes"] > 0 and st_host["d2h_bytes"] > 0
+
+
+def test_host_store_ghz_exact_many_chunks():
+    n, lc, eb = 24, 14, 1e-4
+    q = oracle.quantize(float(np.float32(1 / math.sqrt(2))), eb)
+    expect = np.float32(q * (2 * eb))
+    log("host ghz", n)
+    with _sim(n, "c64", eb, chunk_qubits=lc, store="host") as s:
+        s.init_basis(0)
+        s.apply(ghz(n))
+        a0 = s.amplitudes(0, 64)
+        a1 = s.amplitudes((1 << n) - 64, 64)
+        st = s.stats()
+        zero = s.export_chunk(3)
+    assert a0[0] == expect and a1[-1] == expect
+    assert np.all(a0[1:] == 0) and np.all(a1[:-1] == 0)
+    assert len(zero) == 32 and oracle.codec_header(zero)["kind"] == 0
+    assert st["compressed_bytes"] < 200 * (1 << (n - lc))
