@@ -324,6 +324,13 @@ void msv_destroy(msv_sim *s)
     hipStream_t st = s->stream();
     if (st && !s->poisoned) (void)hipStreamSynchronize(st);
     dev_free(s, s->amps);
+    dev_free(s, s->lam_amps);
+    for (auto &d : s->lam) {
+        dev_free(s, d.W);
+        dev_free(s, d.A);
+        dev_free(s, d.OFF);
+        dev_free(s, d.heap);
+    }
     for (auto &d : s->st) {
         dev_free(s, d.W);
         dev_free(s, d.A);

@@ -15,6 +15,8 @@ enum OpType : int32_t {
     OP_DIAG = 1,    // diagonal over <= 5 arbitrary qubits (tile-local or fixed)
     OP_MFMA = 2,    // dense op run on matrix cores
     OP_PHASE = 3,   // controlled linear phase: factor(g) = A(g) * (b_c(g) ? B(g) : 1)
+    OP_GRAD = 4,    // adjoint probe: per-tile partial <lambda| A |psi> into a gradient slot
+    OP_OBS = 5,     // multiply by the diagonal observable sum_k c_k Z(m_k)
 };
 
 // One kernel-level operation of a pass. Matrices live in a per-apply pool.
@@ -32,6 +34,8 @@ struct OpDesc {
     // of fixed (non-tile) qubits follow: fixA[n], fixB[n].
     int32_t ctrl_pos;      // PHASE: tile-local bit of the control, -1 = fixed or none
     int32_t ctrl_q;        // PHASE: global control qubit, -1 = none
+    int32_t slot;          // GRAD: gradient slot
+    int32_t diag;          // GRAD: 1 = A is diagonal (table in the pool, qubits in gq/pos)
 };
 
 // Geometry and buffers of one pass launch.

@@ -15,6 +15,13 @@ int ensure_stream(msv_sim *s);
 int choose_tile_bits(const msv_sim *s);
 double bound_for(const msv_sim *s, double norm2);
 
+int alloc_device_store(msv_sim *s);
+int pin_stage(msv_sim *s, size_t bytes);
+// Run passes over the device-resident state (plain or compressed). Per-pass
+// (norm, max error, words) triples go to per_pass when given.
+int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOptions &o, double *norm_last,
+                      double *err_last, double *words_last, std::vector<double> *per_pass);
+
 // Host store (compressed chunks in pinned host memory).
 int apply_host_store(msv_sim *s, const std::vector<Prim> &prims, size_t n_gates);
 int init_host_store_basis(msv_sim *s, uint64_t index);

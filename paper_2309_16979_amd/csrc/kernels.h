@@ -34,7 +34,25 @@ struct PassBuffers {
     int32_t check_err;
     const OpDesc *ops;
     const void *pool;            // matrix pool, complex of the state's real type
+    const uint64_t *obs_masks;   // OP_OBS: Z masks and coefficients
+    const double *obs_coeffs;
+    int32_t obs_terms;
 };
+
+// Two states of one adjoint pass: psi and lambda = U^dagger ... O psi. Each
+// gets its own load/store buffers; probe ops write per-tile partials of
+// <lambda| A |psi> to grad_part[2 * (slot * grad_stride + tile)].
+struct AdjointBuffers {
+    PassBuffers psi, lam;
+    double *grad_part;
+    uint64_t grad_stride;
+};
+
+hipError_t launch_adjoint_pass(bool is_double, bool compressed, const PassGeom &geo, const AdjointBuffers &buf,
+                               hipStream_t stream);
+// out[2 s + {0,1}] = sum over tiles of the probe partials of slot s.
+hipError_t launch_grad_reduce(const double *grad_part, uint64_t stride, int n_slots, double *out,
+                              hipStream_t stream);
 
 // Launch one pass over geo.n_tiles tiles. is_double selects complex128.
 // load_c / store_c select compressed (true) or plain amplitudes on each side.

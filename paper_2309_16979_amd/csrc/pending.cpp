@@ -6,11 +6,6 @@ int fail_global(int code, const char *msg);
 }
 
 extern "C" {
-int msv_adjoint(msv_sim *, const msv_gate *, size_t, const double *, size_t, const uint64_t *, const double *, size_t,
-                const size_t *, size_t, double *, double *)
-{
-    return msv::fail_global(MSV_E_UNSUPPORTED, "not available");
-}
 int msv_batch_run(const msv_circuit *, size_t, int, double, const msv_batch_opts *, void *const *, msv_stats *)
 {
     return msv::fail_global(MSV_E_UNSUPPORTED, "not available");

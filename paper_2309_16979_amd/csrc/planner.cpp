@@ -262,6 +262,17 @@ struct Fuser {
 
     void add(const Prim &p)
     {
+        if (p.probe || p.obs) {
+            flush();
+            HostOp op;
+            op.type = p.obs ? OP_OBS : OP_GRAD;
+            op.q = p.q;
+            op.m = p.m;
+            op.slot = p.slot;
+            op.diag = p.diag;
+            out.push_back(op);
+            return;
+        }
         if (p.diag) {
             if (open == DENSE && subset(p.q, Q)) {
                 std::vector<cd> dm((size_t)1 << (2 * p.q.size()), cd(0.0));
@@ -334,7 +345,7 @@ std::vector<Pass> plan_passes(const std::vector<Prim> &prims, const PlanOptions 
         size_t j = i;
         for (; j < prims.size(); ++j) {
             const Prim &p = prims[j];
-            if (p.diag) continue;
+            if (p.diag || p.obs) continue;
             std::vector<int> U = unite(L, p.q);
             if ((int)U.size() > tb) break;
             L = U;
@@ -393,6 +404,8 @@ bool lower_passes(const std::vector<Pass> &passes, const PlanOptions &o, std::ve
             d.mat = (int32_t)(pool.size() / 2);
             d.ctrl_pos = -1;
             d.ctrl_q = -1;
+            d.slot = -1;
+            d.diag = 0;
             for (int m = 0; m < 5; ++m) { d.pos[m] = -1; d.gq[m] = -1; }
             if (h.type == OP_DENSE) {
                 d.k = (int32_t)h.q.size();
@@ -405,6 +418,20 @@ bool lower_passes(const std::vector<Pass> &passes, const PlanOptions &o, std::ve
                 ok = ok && (h.ctrl_mask & tmask) == 0;
                 d.ctrl_fixed = h.ctrl_mask;
                 for (const cd &v : h.m) push(v);
+            } else if (h.type == OP_GRAD) {
+                d.k = (int32_t)h.q.size();
+                d.slot = h.slot;
+                d.diag = h.diag ? 1 : 0;
+                ok = ok && d.k >= 1 && d.k <= 2 && h.slot >= 0 &&
+                     (int)h.m.size() == (h.diag ? (1 << d.k) : (1 << (2 * d.k)));
+                for (int m = 0; m < d.k; ++m) {
+                    d.gq[m] = h.q[m];
+                    d.pos[m] = tpos(h.q[m]);
+                    ok = ok && (h.diag || d.pos[m] >= 0);
+                }
+                for (const cd &v : h.m) push(v);
+            } else if (h.type == OP_OBS) {
+                d.k = 0;
             } else if (h.type == OP_DIAG) {
                 d.k = (int32_t)h.q.size();
                 ok = ok && d.k >= 1 && d.k <= 5 && (int)h.m.size() == (1 << d.k);

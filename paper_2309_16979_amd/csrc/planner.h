@@ -29,6 +29,9 @@ struct Prim {
     int param = -1;           // parameter index of the source gate (adjoint)
     int kind = -1;            // source gate kind
     size_t gate = 0;          // index of the source gate
+    bool probe = false;       // adjoint probe: <lambda| A |psi> into gradient slot `slot`
+    int slot = -1;
+    bool obs = false;         // multiply by the diagonal observable (lambda = O psi)
 };
 
 struct HostOp {
@@ -40,6 +43,8 @@ struct HostOp {
     int hub = -1;
     std::vector<double> mu, lam;
     cd global = 1.0;
+    int slot = -1;            // probe
+    bool diag = false;        // probe with a diagonal A
 };
 
 struct Pass {

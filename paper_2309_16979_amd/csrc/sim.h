@@ -88,6 +88,9 @@ struct msv_sim {
     msv::DevMem amps;          // uncompressed state (eb = 0)
     msv::DevStore st[2];       // device store ping-pong
     int cur = 0;
+    msv::DevMem lam_amps;      // adjoint: lambda (uncompressed)
+    msv::DevStore lam[2];      // adjoint: lambda (compressed)
+    int lcur = 0;
     msv::HostStore hs;         // host store
     msv::Workspace ws;
     double scale = 1.0;        // pending renormalisation factor, applied at decode

@@ -1,0 +1,468 @@
+// Device-side building blocks of a tile pass, shared by the single-state pass
+// kernel and the two-state adjoint kernel.
+//
+// A tile is 2^TB amplitudes held in LDS as two planes (re, im). Tile-local bit
+// i is global qubit geo.tile_q[i]; bits 0..5 are qubits 0..5, so a tile is a
+// set of whole 64-amplitude codec blocks. Every function here is called by
+// all threads of the workgroup.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "codec_device.h"
+#include "kernels.h"
+
+namespace msv {
+
+template <typename T> struct Cplx;
+template <> struct Cplx<float> { using V = float2; };
+template <> struct Cplx<double> { using V = double2; };
+
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+__device__ __forceinline__ uint64_t block_index(const BlockStore &s, uint64_t B)
+{
+    if (!s.chunk_slot) return B;
+    const uint64_t nbm = (1ull << s.log2_nb) - 1;
+    return ((uint64_t)s.chunk_slot[B >> s.log2_nb] << s.log2_nb) | (B & nbm);
+}
+
+// ------------------------------------------------------------- geometry
+
+// Global index of the tile's amplitude 0: the tile id's bits deposited into
+// the non-tile positions in ascending order.
+__device__ __forceinline__ uint64_t tile_base(const PassGeom &geo, uint64_t tile)
+{
+    uint64_t base = 0, m = geo.nontile_mask, t = tile;
+    while (m) {
+        const uint64_t low = m & (~m + 1ull);
+        if (t & 1ull) base |= low;
+        t >>= 1;
+        m &= m - 1;
+    }
+    return base;
+}
+
+// sG[jb] = global 64-amplitude block index of tile block jb.
+template <int TB>
+__device__ __forceinline__ void tile_blocks(const PassGeom &geo, uint64_t base, uint64_t *sG)
+{
+    constexpr int NAB = 1 << (TB - 6);
+    for (int jb = threadIdx.x; jb < NAB; jb += kThreads) {
+        uint64_t G = base >> 6;
+#pragma unroll
+        for (int i = 0; i < TB - 6; ++i)
+            if ((jb >> i) & 1) G |= 1ull << (geo.tile_q[6 + i] - 6);
+        sG[jb] = G;
+    }
+}
+
+// ------------------------------------------------------------------ load
+
+template <typename T, int TB, bool LOADC>
+__device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, const void *amps, const BlockStore &in,
+                                          double step, double sc, int wave, int lane)
+{
+    constexpr int NAB = 1 << (TB - 6), NSB = 2 * NAB, NW = kThreads / 64;
+    using V2 = typename Cplx<T>::V;
+    if (!LOADC) {
+        const V2 *a = (const V2 *)amps;
+        const T scale = (T)sc;
+        for (int jb = wave; jb < NAB; jb += NW) {
+            V2 v = a[(sG[jb] << 6) | (uint64_t)lane];
+            if (sc != 1.0) { v.x *= scale; v.y *= scale; }
+            sre[jb * 64 + lane] = v.x;
+            sim[jb * 64 + lane] = v.y;
+        }
+    } else {
+        const T scale = (T)sc;
+        for (int bt = wave; bt < NSB; bt += NW) {
+            const int jb = bt >> 1, p = bt & 1;
+            const uint64_t bi = block_index(in, 2 * sG[jb] + (uint64_t)p);
+            const uint32_t W = in.W[bi];
+            const int32_t A = in.A[bi];
+            uint64_t mine = 0;
+            if (W) {
+                const uint64_t off = in.OFF[bi];
+                if ((uint32_t)lane < W) mine = in.heap[off + lane];
+            }
+            T x = dequantize<T>(unpack_codes(mine, W, A), step);
+            if (sc != 1.0) x *= scale;
+            (p ? sim : sre)[jb * 64 + lane] = x;
+        }
+    }
+}
+
+// ----------------------------------------------------------------- store
+
+// Store the tile (plain or encoded). nrm / err accumulate this thread's FP64
+// sum |x|^2 and max |x - x'|; the return value is the tile's payload words
+// (valid in every thread). The codec scratch sW / sA / sOff holds NSB entries.
+template <typename T, int TB, bool STOREC>
+__device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *sG, uint32_t *sW, int32_t *sA,
+                                               uint32_t *sOff, void *amps, const BlockStore &out, uint64_t slot,
+                                               double inv_step, double step, int check, uint32_t *flags,
+                                               double &nrm, double &err, int wave, int lane)
+{
+    constexpr int NAB = 1 << (TB - 6), NSB = 2 * NAB, NW = kThreads / 64;
+    constexpr int VPT = sizeof(T) / 4;
+    using V2 = typename Cplx<T>::V;
+    if (!STOREC) {
+        V2 *a = (V2 *)amps;
+        for (int jb = wave; jb < NAB; jb += NW) {
+            V2 v;
+            v.x = sre[jb * 64 + lane];
+            v.y = sim[jb * 64 + lane];
+            const double xr = v.x, xi = v.y;
+            nrm += xr * xr + xi * xi;
+            a[(sG[jb] << 6) | (uint64_t)lane] = v;
+        }
+        return 0;
+    }
+    bool bad = false;
+    // E1: codes, residuals, widths; the zigzag residual replaces the value in LDS
+    for (int bt = wave; bt < NSB; bt += NW) {
+        const int jb = bt >> 1, p = bt & 1;
+        T *plane = p ? sim : sre;
+        const T x = plane[jb * 64 + lane];
+        const double xd = (double)x;
+        nrm += xd * xd;
+        const int32_t q = quantize<T>(x, inv_step, bad);
+        if (check) {
+            const T xr = dequantize<T>(q, step);
+            err = fmax(err, __builtin_fabs(xd - (double)xr));
+        }
+        const uint32_t u = residual_zigzag(q);
+        const uint32_t W = block_width(u);
+        const int32_t A = __builtin_amdgcn_readlane(q, 0);
+        reinterpret_cast<uint32_t *>(plane)[(jb * 64 + lane) * VPT] = u;
+        if (lane == 0) { sW[bt] = W; sA[bt] = A; }
+    }
+    if (bad) atomicOr(flags, 1u);
+    __syncthreads();
+    // E2: exclusive scan of the widths over the tile's blocks
+    if (wave == 0) {
+        constexpr int PER = (NSB + 63) / 64;
+        uint32_t v[PER];
+        uint32_t s = 0;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int idx = lane * PER + i;
+            v[i] = idx < NSB ? sW[idx] : 0u;
+            s += v[i];
+        }
+        uint32_t ex = wave_inclusive_sum(s) - s;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int idx = lane * PER + i;
+            if (idx < NSB) sOff[idx] = ex;
+            ex += v[i];
+        }
+    }
+    __syncthreads();
+    // E3: bit planes into this tile's heap slot
+    for (int bt = wave; bt < NSB; bt += NW) {
+        const int jb = bt >> 1, p = bt & 1;
+        const T *plane = p ? sim : sre;
+        const uint32_t u = reinterpret_cast<const uint32_t *>(plane)[(jb * 64 + lane) * VPT];
+        const uint32_t W = sW[bt];
+        const uint64_t mine = pack_planes(u, W);
+        const uint64_t off = slot + sOff[bt];
+        if ((uint32_t)lane < W) out.heap[off + lane] = mine;
+        if (lane == 0) {
+            const uint64_t bi = block_index(out, 2 * sG[jb] + (uint64_t)p);
+            out.W[bi] = (uint8_t)W;
+            out.A[bi] = sA[bt];
+            out.OFF[bi] = (uint32_t)off;
+        }
+    }
+    return sOff[NSB - 1] + sW[NSB - 1];
+}
+
+// ------------------------------------------------------------------- ops
+
+// Dense 2^K x 2^K complex matrix on tile-local bits op.pos[0..K), matrix index
+// s = sum_m b(pos[m]) 2^m. Each work item loads its group of 2^K amplitudes
+// into registers and writes RPT output rows; when there are fewer groups than
+// threads, adjacent lanes of one wave share a group (all loads of a wave are
+// issued before its stores, so sharing is race-free).
+template <typename T, int TB, int K>
+__device__ __forceinline__ void op_dense(T *__restrict__ sre, T *__restrict__ sim, const OpDesc &op,
+                                         const T *__restrict__ M)
+{
+    constexpr int D = 1 << K;
+    constexpr int NG = (1 << TB) >> K;
+    constexpr int TPG0 = NG >= kThreads ? 1 : kThreads / NG;
+    constexpr int TPG = TPG0 < D ? TPG0 : D;
+    constexpr int RPT = D / TPG;
+    int sp[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) sp[m] = op.pos[m];
+#pragma unroll
+    for (int i = 1; i < K; ++i)
+#pragma unroll
+        for (int j = i; j > 0; --j)
+            if (sp[j - 1] > sp[j]) { int t = sp[j]; sp[j] = sp[j - 1]; sp[j - 1] = t; }
+    int offs[D];
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+        int o = 0;
+#pragma unroll
+        for (int m = 0; m < K; ++m)
+            if ((s >> m) & 1) o |= 1 << op.pos[m];
+        offs[s] = o;
+    }
+    const int cl = (int)op.ctrl_local;
+    for (int w = threadIdx.x; w < NG * TPG; w += kThreads) {
+        const int g = w / TPG, rb = w % TPG;
+        int l0 = g;
+#pragma unroll
+        for (int m = 0; m < K; ++m) l0 = ((l0 >> sp[m]) << (sp[m] + 1)) | (l0 & ((1 << sp[m]) - 1));
+        if ((l0 & cl) != cl) continue;
+        T vr[D], vi[D];
+#pragma unroll
+        for (int s = 0; s < D; ++s) { vr[s] = sre[l0 + offs[s]]; vi[s] = sim[l0 + offs[s]]; }
+#pragma unroll
+        for (int rr = 0; rr < RPT; ++rr) {
+            const int r = rb * RPT + rr;
+            T ar = 0, ai = 0;
+#pragma unroll
+            for (int s = 0; s < D; ++s) {
+                const T mr = M[2 * (r * D + s)], mi = M[2 * (r * D + s) + 1];
+                ar = fmaT(mr, vr[s], ar);
+                ar = fmaT(-mi, vi[s], ar);
+                ai = fmaT(mr, vi[s], ai);
+                ai = fmaT(mi, vr[s], ai);
+            }
+            int lr = l0;
+#pragma unroll
+            for (int s = 0; s < D; ++s)
+                if (s == r) lr = l0 + offs[s];
+            sre[lr] = ar;
+            sim[lr] = ai;
+        }
+    }
+}
+
+// Bit s of a diagonal table index: table bit m is global qubit gq[m], taken
+// from the tile-local index (pos[m] >= 0) or from the tile's base.
+template <int K>
+__device__ __forceinline__ int diag_fixed_bits(const OpDesc &op, uint64_t base)
+{
+    int fixed_s = 0;
+#pragma unroll
+    for (int m = 0; m < K; ++m)
+        if (op.pos[m] < 0) fixed_s |= (int)((base >> op.gq[m]) & 1ull) << m;
+    return fixed_s;
+}
+
+template <int K>
+__device__ __forceinline__ int diag_index(const OpDesc &op, int fixed_s, int l)
+{
+    int s = fixed_s;
+#pragma unroll
+    for (int m = 0; m < K; ++m)
+        if (op.pos[m] >= 0) s |= ((l >> op.pos[m]) & 1) << m;
+    return s;
+}
+
+// Diagonal over K qubits: amplitude *= d[s].
+template <typename T, int TB, int K>
+__device__ __forceinline__ void op_diag(T *__restrict__ sre, T *__restrict__ sim, const OpDesc &op,
+                                        const T *__restrict__ dv, uint64_t base)
+{
+    const int fixed_s = diag_fixed_bits<K>(op, base);
+    for (int l = threadIdx.x; l < (1 << TB); l += kThreads) {
+        const int s = diag_index<K>(op, fixed_s, l);
+        const T dr = dv[2 * s], di = dv[2 * s + 1];
+        const T xr = sre[l], xi = sim[l];
+        sre[l] = fmaT(xr, dr, -xi * di);
+        sim[l] = fmaT(xr, di, xi * dr);
+    }
+}
+
+// Controlled linear phase (a run of diagonal gates sharing one control c):
+//   factor(g) = A(g) * (b_c(g) ? B(g) : 1),
+// A and B products of per-qubit phases. Tile-local qubits factor through two
+// tables indexed by the low 6 bits and by the high TB-6 bits; qubits outside
+// the tile contribute a per-tile constant built from per-qubit factors.
+template <typename T, int TB>
+__device__ __forceinline__ void op_phase(T *__restrict__ sre, T *__restrict__ sim, const OpDesc &op,
+                                         const T *__restrict__ tab, uint64_t base, int n, T *__restrict__ scratch)
+{
+    constexpr int NH = 1 << (TB - 6);
+    const T *loA = tab, *hiA = tab + 2 * 64, *loB = tab + 2 * (64 + NH), *hiB = tab + 2 * (128 + NH);
+    const T *fixA = tab + 2 * (128 + 2 * NH), *fixB = fixA + 2 * n;
+    T ar = 1, ai = 0, br = 1, bi = 0;
+    const uint64_t fm = base & op.ctrl_fixed;  // ctrl_fixed holds the non-tile qubit mask here
+    for (int q = 0; q < n; ++q) {
+        if (!((fm >> q) & 1ull)) continue;
+        T fr = fixA[2 * q], fi = fixA[2 * q + 1];
+        T tr = ar * fr - ai * fi;
+        ai = ar * fi + ai * fr;
+        ar = tr;
+        fr = fixB[2 * q];
+        fi = fixB[2 * q + 1];
+        tr = br * fr - bi * fi;
+        bi = br * fi + bi * fr;
+        br = tr;
+    }
+    bool ctrl_fixed_on = true;
+    if (op.ctrl_q >= 0 && op.ctrl_pos < 0) ctrl_fixed_on = (base >> op.ctrl_q) & 1ull;
+    // scratch: lo0 = loA * A_fix (control 0), lo1 = loA * loB * A_fix * B_fix, hi1 = hiA * hiB
+    T *lo0 = scratch, *lo1 = scratch + 128, *hi0 = scratch + 256, *hi1 = scratch + 256 + 2 * NH;
+    for (int i = threadIdx.x; i < 64; i += kThreads) {
+        const T xr = loA[2 * i], xi = loA[2 * i + 1];
+        const T r0 = xr * ar - xi * ai, i0 = xr * ai + xi * ar;
+        lo0[2 * i] = r0;
+        lo0[2 * i + 1] = i0;
+        const T yr = loB[2 * i], yi = loB[2 * i + 1];
+        const T cr = br * yr - bi * yi, ci = br * yi + bi * yr;
+        lo1[2 * i] = r0 * cr - i0 * ci;
+        lo1[2 * i + 1] = r0 * ci + i0 * cr;
+    }
+    for (int i = threadIdx.x; i < NH; i += kThreads) {
+        const T xr = hiA[2 * i], xi = hiA[2 * i + 1];
+        const T yr = hiB[2 * i], yi = hiB[2 * i + 1];
+        hi0[2 * i] = xr;
+        hi0[2 * i + 1] = xi;
+        hi1[2 * i] = xr * yr - xi * yi;
+        hi1[2 * i + 1] = xr * yi + xi * yr;
+    }
+    __syncthreads();
+    const int cp = op.ctrl_pos;
+    const bool has_ctrl = op.ctrl_q >= 0;
+    for (int l = threadIdx.x; l < (1 << TB); l += kThreads) {
+        const bool on = has_ctrl && (cp >= 0 ? ((l >> cp) & 1) != 0 : ctrl_fixed_on);
+        const T *lo = on ? lo1 : lo0;
+        const T *hi = on ? hi1 : hi0;
+        const int a = l & 63, h = l >> 6;
+        const T fr = lo[2 * a], fi = lo[2 * a + 1];
+        const T gr = hi[2 * h], gi = hi[2 * h + 1];
+        const T pr = fr * gr - fi * gi, pi = fr * gi + fi * gr;
+        const T xr = sre[l], xi = sim[l];
+        sre[l] = fmaT(xr, pr, -xi * pi);
+        sim[l] = fmaT(xr, pi, xi * pr);
+    }
+}
+
+// LDS scratch (in T) needed by op_phase.
+template <int TB> struct PhaseScratch { static constexpr int size = 2 * (128 + 2 * (1 << (TB - 6))); };
+
+// Multiply every amplitude by the real diagonal sum_k c_k (-1)^popcount(g & m_k).
+template <typename T, int TB>
+__device__ __forceinline__ void op_obs(T *__restrict__ sre, T *__restrict__ sim, const uint64_t *sG,
+                                       const uint64_t *__restrict__ masks, const double *__restrict__ coeffs,
+                                       int n_terms)
+{
+    for (int l = threadIdx.x; l < (1 << TB); l += kThreads) {
+        const uint64_t g = (sG[l >> 6] << 6) | (uint64_t)(l & 63);
+        double v = 0.0;
+        for (int t = 0; t < n_terms; ++t) v += (__popcll(g & masks[t]) & 1) ? -coeffs[t] : coeffs[t];
+        sre[l] = (T)(sre[l] * v);
+        sim[l] = (T)(sim[l] * v);
+    }
+}
+
+// One op (dense, diagonal, phase) on one tile. Ends without a barrier.
+template <typename T, int TB>
+__device__ __forceinline__ void apply_op(T *sre, T *sim, const OpDesc &op, const T *M, uint64_t base, int n,
+                                         T *sph)
+{
+    if (op.type == OP_DENSE || op.type == OP_MFMA) {
+        if (op.ctrl_fixed == 0 || (base & op.ctrl_fixed) == op.ctrl_fixed) {
+            switch (op.k) {
+            case 1: op_dense<T, TB, 1>(sre, sim, op, M); break;
+            case 2: op_dense<T, TB, 2>(sre, sim, op, M); break;
+            case 3: op_dense<T, TB, 3>(sre, sim, op, M); break;
+            case 4: op_dense<T, TB, 4>(sre, sim, op, M); break;
+            default: op_dense<T, TB, 5>(sre, sim, op, M); break;
+            }
+        }
+    } else if (op.type == OP_DIAG) {
+        switch (op.k) {
+        case 1: op_diag<T, TB, 1>(sre, sim, op, M, base); break;
+        case 2: op_diag<T, TB, 2>(sre, sim, op, M, base); break;
+        case 3: op_diag<T, TB, 3>(sre, sim, op, M, base); break;
+        case 4: op_diag<T, TB, 4>(sre, sim, op, M, base); break;
+        default: op_diag<T, TB, 5>(sre, sim, op, M, base); break;
+        }
+    } else if (op.type == OP_PHASE) {
+        op_phase<T, TB>(sre, sim, op, M, base, n, sph);
+    }
+}
+
+// Per-thread FP64 partial of <lambda| A |psi> over the tile for a probe op:
+// A dense on tile bits (k <= 2) or diagonal (table of 2^k entries).
+template <typename T, int TB, int K>
+__device__ __forceinline__ void probe_dense(const T *pre, const T *pim, const T *lre, const T *lim, const OpDesc &op,
+                                            const T *__restrict__ M, double &accr, double &acci)
+{
+    constexpr int D = 1 << K;
+    constexpr int NG = (1 << TB) >> K;
+    int sp[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) sp[m] = op.pos[m];
+    if (K == 2 && sp[0] > sp[1]) { int t = sp[0]; sp[0] = sp[1]; sp[1] = t; }
+    int offs[D];
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+        int o = 0;
+#pragma unroll
+        for (int m = 0; m < K; ++m)
+            if ((s >> m) & 1) o |= 1 << op.pos[m];
+        offs[s] = o;
+    }
+    for (int g = threadIdx.x; g < NG; g += kThreads) {
+        int l0 = g;
+#pragma unroll
+        for (int m = 0; m < K; ++m) l0 = ((l0 >> sp[m]) << (sp[m] + 1)) | (l0 & ((1 << sp[m]) - 1));
+        double vr[D], vi[D];
+#pragma unroll
+        for (int s = 0; s < D; ++s) { vr[s] = pre[l0 + offs[s]]; vi[s] = pim[l0 + offs[s]]; }
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            double ar = 0.0, ai = 0.0;
+#pragma unroll
+            for (int s = 0; s < D; ++s) {
+                const double mr = M[2 * (r * D + s)], mi = M[2 * (r * D + s) + 1];
+                ar += mr * vr[s] - mi * vi[s];
+                ai += mr * vi[s] + mi * vr[s];
+            }
+            const double yr = lre[l0 + offs[r]], yi = lim[l0 + offs[r]];
+            accr += yr * ar + yi * ai;   // conj(lambda) * (A psi)
+            acci += yr * ai - yi * ar;
+        }
+    }
+}
+
+template <typename T, int TB, int K>
+__device__ __forceinline__ void probe_diag(const T *pre, const T *pim, const T *lre, const T *lim, const OpDesc &op,
+                                           const T *__restrict__ dv, uint64_t base, double &accr, double &acci)
+{
+    const int fixed_s = diag_fixed_bits<K>(op, base);
+    for (int l = threadIdx.x; l < (1 << TB); l += kThreads) {
+        const int s = diag_index<K>(op, fixed_s, l);
+        const double dr = dv[2 * s], di = dv[2 * s + 1];
+        const double xr = pre[l], xi = pim[l];
+        const double ar = dr * xr - di * xi, ai = dr * xi + di * xr;
+        const double yr = lre[l], yi = lim[l];
+        accr += yr * ar + yi * ai;
+        acci += yr * ai - yi * ar;
+    }
+}
+
+template <typename T, int TB>
+__device__ __forceinline__ void probe(const T *pre, const T *pim, const T *lre, const T *lim, const OpDesc &op,
+                                      const T *M, uint64_t base, double &accr, double &acci)
+{
+    if (op.diag) {
+        if (op.k == 1) probe_diag<T, TB, 1>(pre, pim, lre, lim, op, M, base, accr, acci);
+        else probe_diag<T, TB, 2>(pre, pim, lre, lim, op, M, base, accr, acci);
+    } else {
+        if (op.k == 1) probe_dense<T, TB, 1>(pre, pim, lre, lim, op, M, accr, acci);
+        else probe_dense<T, TB, 2>(pre, pim, lre, lim, op, M, accr, acci);
+    }
+}
+
+}  // namespace msv

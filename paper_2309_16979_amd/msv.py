@@ -177,6 +177,24 @@ class Simulator:
         self._chk(self._L.msv_get_stats(self.h, C.byref(st)))
         return st.as_dict()
 
+    def adjoint(self, gates: Sequence, params, masks, coeffs, checkpoints: Sequence[int] = ()):
+        """Expectation of sum_k c_k Z(m_k) after `gates` (parameterised gates
+        take theta = params[gate.param]) from the current state, and its
+        gradient, by the adjoint method with compressed checkpoints before the
+        given gate indices. The state is left unchanged."""
+        arr, keep = gate_array(gates)
+        p = np.ascontiguousarray(params, dtype=np.float64).ravel()
+        m = np.ascontiguousarray(list(masks), dtype=np.uint64)
+        c = np.ascontiguousarray(list(coeffs), dtype=np.float64)
+        ck = np.ascontiguousarray(list(checkpoints), dtype=np.uint64)
+        grad = np.zeros(max(1, p.size), dtype=np.float64)
+        ev = C.c_double()
+        self._chk(self._L.msv_adjoint(self.h, arr, len(gates), p.ctypes.data, p.size, m.ctypes.data,
+                                      c.ctypes.data, len(m), ck.ctypes.data if ck.size else None, ck.size,
+                                      C.byref(ev), grad.ctypes.data))
+        del keep
+        return ev.value, grad[: p.size]
+
     def export_chunk(self, chunk: int) -> bytes:
         need = C.c_size_t(0)
         code = self._L.msv_export_chunk(self.h, chunk, None, 0, C.byref(need))
@@ -212,3 +230,35 @@ def codec_decode(blob: bytes, dtype: str = "c64") -> np.ndarray:
     out = np.zeros(1 << log2c, dtype=np.complex128 if _DT[dtype] == L.C128 else np.complex64)
     check(load().msv_codec_decode(_DT[dtype], b.ctypes.data, len(blob), out.ctypes.data))
     return out
+
+
+def _autograd():
+    import torch
+
+    class AdjointExpectation(torch.autograd.Function):
+        """<psi(theta)| O |psi(theta)> with the adjoint-method gradient.
+
+        forward(params, sim, gates, init_basis, masks, coeffs, checkpoints):
+        params is a 1-D float64 tensor; the simulator's state is set to
+        |init_basis> and the circuit evaluated by msv_adjoint, which also
+        yields the gradient used by backward."""
+
+        @staticmethod
+        def forward(ctx, params, sim, gates, init_basis, masks, coeffs, checkpoints=()):
+            sim.init_basis(init_basis)
+            p = params.detach().to("cpu", torch.float64).numpy()
+            ev, grad = sim.adjoint(gates, p, masks, coeffs, checkpoints)
+            ctx.save_for_backward(torch.from_numpy(grad).to(params.device, params.dtype))
+            return params.new_tensor(ev)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (g,) = ctx.saved_tensors
+            return grad_out * g, None, None, None, None, None, None
+
+    return AdjointExpectation
+
+
+def adjoint_expectation(params, sim, gates, init_basis, masks, coeffs, checkpoints=()):
+    """Differentiable expectation (torch): see AdjointExpectation."""
+    return _autograd().apply(params, sim, gates, init_basis, masks, coeffs, tuple(checkpoints))
