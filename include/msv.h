@@ -135,7 +135,9 @@ int msv_set_fusion(msv_sim *sim, int k_max, int mma_precision);
  *   "check_bound"  1 (default) = FP64 max |x - x'| per pass
  *   "mfma_min_k"   smallest fused width run on matrix cores (3..6; 6 = never)
  *   "batch_chunks" host store: chunks per streamed batch (0 = automatic)
- *   "time_passes"  1 = time every pass kernel with events (msv_stats.t_pass) */
+ *   "time_passes"  1 = time every pass kernel with events (msv_stats.t_pass)
+ *   "autotune"     1 = choose fusion width and tile size per msv_apply from a
+ *                  cost model calibrated once per process on the GPU */
 int msv_set_option(msv_sim *sim, const char *key, double value);
 /* Device memory provider (e.g. a framework's caching allocator). alloc returns
  * NULL on failure; both are called on the calling thread. Without it the

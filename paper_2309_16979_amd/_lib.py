@@ -78,6 +78,14 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libmsv.so is not built: run `python -m paper_2309_16979_amd.build` "
                           "(or __graft_entry__.build())")
+    # One HIP runtime per process: torch ships its own copy of the HIP and HSA
+    # runtimes under the same sonames, and its libraries ask for them by an
+    # unversioned name. Loading torch first makes libmsv bind to that copy;
+    # loading libmsv first would put a second, competing runtime in the process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     P = C.c_void_p
     sig = {

@@ -409,6 +409,8 @@ int msv_set_option(msv_sim *s, const char *key, double v)
     } else if (!strcmp(key, "mfma_min_k")) {
         if (v != iv || iv < 3 || iv > 6) return fail(s, MSV_E_ARG, "mfma_min_k in 3..6");
         s->mfma_min_k = iv;
+    } else if (!strcmp(key, "autotune")) {
+        s->autotune = v != 0.0;
     } else if (!strcmp(key, "time_passes")) {
         s->time_passes = v != 0.0;
     } else if (!strcmp(key, "batch_chunks")) {
@@ -578,7 +580,15 @@ int msv_apply(msv_sim *s, const msv_gate *gates, size_t n_gates)
         o.tb = choose_tile_bits(s);
         o.k_max = s->k_max;
         o.mfma_min_k = s->mfma_min_k;
-        std::vector<Pass> passes = plan_passes(prims, o);
+        std::vector<Pass> passes;
+        if (s->autotune && s->compressed()) {
+            int k = o.k_max, tb = o.tb;
+            if ((st = autotune(s->is_double(), s->stream(), prims, s->n, &k, &tb, &passes))) return st;
+            o.k_max = s->tuned_k = k;
+            o.tb = s->tuned_tb = tb;
+        } else {
+            passes = plan_passes(prims, o);
+        }
         size_t n_ops = 0;
         for (auto &p : passes) n_ops += p.ops.size();
         double norm = 0.0, err_last = 0.0, words = 0.0;

@@ -22,6 +22,10 @@ int pin_stage(msv_sim *s, size_t bytes);
 int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOptions &o, double *norm_last,
                       double *err_last, double *words_last, std::vector<double> *per_pass);
 
+// Autotuner: fusion width and tile size minimising the calibrated cost model.
+int autotune(bool is_double, hipStream_t stream, const std::vector<Prim> &prims, int n, int *k_out, int *tb_out,
+             std::vector<Pass> *out);
+
 // Host store (compressed chunks in pinned host memory).
 int apply_host_store(msv_sim *s, const std::vector<Prim> &prims, size_t n_gates);
 int init_host_store_basis(msv_sim *s, uint64_t index);

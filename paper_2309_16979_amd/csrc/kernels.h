@@ -48,6 +48,20 @@ struct AdjointBuffers {
     uint64_t grad_stride;
 };
 
+// One (circuit or parameter set, pass) of a batched launch. The item's
+// workgroups cover tiles [geo.tile_begin, geo.tile_begin + geo.n_tiles); its
+// per-tile statistics go to buf.part[3 * local tile].
+struct BatchItem {
+    PassGeom geo;
+    PassBuffers buf;
+};
+
+// Run every item's pass in one launch of sum(n_tiles) workgroups;
+// prefix[i] = first workgroup of item i (prefix[0] = 0). All items share tb
+// and the compressed device layout.
+hipError_t launch_batch_pass(bool is_double, int tb, const BatchItem *items, const uint64_t *prefix, int n_items,
+                             uint64_t total_tiles, hipStream_t stream);
+
 hipError_t launch_adjoint_pass(bool is_double, bool compressed, const PassGeom &geo, const AdjointBuffers &buf,
                                hipStream_t stream);
 // out[2 s + {0,1}] = sum over tiles of the probe partials of slot s.

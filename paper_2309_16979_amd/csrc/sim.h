@@ -78,6 +78,8 @@ struct msv_sim {
     int k_max = 2, mma = MSV_MMA_F32, tile_bits = 0, renorm = 0, check_bound = 1, mfma_min_k = 6;
     int batch_chunks = 0;
     int time_passes = 0;
+    int autotune = 0;
+    int tuned_k = 0, tuned_tb = 0;   // last autotuner choice
     void *(*alloc)(size_t, void *) = nullptr;
     void (*dealloc)(void *, void *) = nullptr;
     void *actx = nullptr;

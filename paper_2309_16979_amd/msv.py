@@ -232,6 +232,47 @@ def codec_decode(blob: bytes, dtype: str = "c64") -> np.ndarray:
     return out
 
 
+def batch_run(circuits, dtype: str = "c64", eb: float = 1e-4, autotune: bool = True, k_max: int = 2,
+              log2_tile: int = 0, mma: str = "f32", want_amplitudes: bool = False):
+    """Run many circuits, each given as (n, gates, init_basis), with one launch
+    per pass level. Returns (stats dict, list of amplitude arrays or None)."""
+    Lb = load()
+    arrs, keeps = [], []
+    cs = (L.Circuit * len(circuits))()
+    for i, (n, gates, x) in enumerate(circuits):
+        arr, keep = gate_array(gates)
+        arrs.append(arr)
+        keeps.append(keep)
+        cs[i] = L.Circuit(n, arr, len(gates), int(x))
+    opts = L.BatchOpts(1 if autotune else 0, k_max, log2_tile, _MMA[mma])
+    npdt = np.complex128 if _DT[dtype] == L.C128 else np.complex64
+    outs = [np.empty(1 << n, dtype=npdt) for n, _, _ in circuits] if want_amplitudes else None
+    ptrs = (C.c_void_p * len(circuits))(*[o.ctypes.data for o in outs]) if outs else None
+    st = L.Stats()
+    check(Lb.msv_batch_run(cs, len(circuits), _DT[dtype], float(eb), C.byref(opts), ptrs, C.byref(st)))
+    return st.as_dict(), outs
+
+
+def batch_adjoint(n, gates, params_sets, masks, coeffs, checkpoints=(), dtype: str = "c64", eb: float = 0.0,
+                  init_basis: int = 0):
+    """Adjoint expectation and gradient of one ansatz for each row of params_sets."""
+    Lb = load()
+    arr, keep = gate_array(gates)
+    circ = L.Circuit(n, arr, len(gates), int(init_basis))
+    P = np.ascontiguousarray(params_sets, dtype=np.float64)
+    n_sets, n_params = P.shape
+    m = np.ascontiguousarray(list(masks), dtype=np.uint64)
+    c = np.ascontiguousarray(list(coeffs), dtype=np.float64)
+    ck = np.ascontiguousarray(list(checkpoints), dtype=np.uint64)
+    ev = np.zeros(n_sets)
+    gr = np.zeros((n_sets, n_params))
+    check(Lb.msv_batch_adjoint(C.byref(circ), P.ctypes.data, n_sets, n_params, m.ctypes.data, c.ctypes.data,
+                               len(m), ck.ctypes.data if ck.size else None, ck.size, _DT[dtype], float(eb),
+                               ev.ctypes.data, gr.ctypes.data))
+    del keep
+    return ev, gr
+
+
 def _autograd():
     import torch
 

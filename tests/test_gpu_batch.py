@@ -1,0 +1,61 @@
+"""Batched runs: one launch per pass level over many uneven circuits; each
+circuit's result must equal its single-circuit GPU run (same plan) bitwise and
+meet the pass bound; fidelity against the oracle for small members."""
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.gpu_util import ensure_built, log
+from workloads import ansatz, ansatz_params, batch_circuits, zz_chain
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    ensure_built()
+
+
+def test_batch_equals_single_runs_bitwise():
+    from paper_2309_16979_amd import Simulator, batch_run
+    circs = batch_circuits(12, seed=100, n_lo=10, n_hi=16, d_lo=5, d_hi=20)
+    eb = 1e-5
+    log("batch fixed k/tile")
+    st, outs = batch_run([(n, g, 0) for n, g in circs], eb=eb, autotune=False, k_max=2, log2_tile=10,
+                         want_amplitudes=True)
+    assert st["bound_violations"] == 0 and st["kernel_launches"] >= 1
+    for (n, g), a in zip(circs, outs):
+        with Simulator(n, dtype="c64", eb=eb, chunk_qubits=min(n, 20), k_max=2,
+                       options={"tile_qubits": min(10, n)}) as s:
+            s.init_basis(0)
+            s.apply(g)
+            ref = s.amplitudes()
+        assert np.array_equal(a.view(np.uint8), ref.view(np.uint8)), n
+        f = oracle.fidelity(oracle.simulate(n, g, 0), a)[1]
+        assert f > 0.999, (n, f)
+
+
+def test_batch_autotuned_uneven_sizes():
+    from paper_2309_16979_amd import batch_run
+    circs = batch_circuits(24, seed=7, n_lo=12, n_hi=18, d_lo=10, d_hi=30)
+    log("batch autotuned")
+    st, outs = batch_run([(n, g, 0) for n, g in circs], eb=1e-5, autotune=True, want_amplitudes=True)
+    assert st["bound_violations"] == 0
+    for (n, g), a in list(zip(circs, outs))[:6]:
+        f = oracle.fidelity(oracle.simulate(n, g, 0), a)[1]
+        assert f > 0.999, (n, f)
+
+
+def test_batch_adjoint_matches_single_adjoint():
+    from paper_2309_16979_amd import Simulator, batch_adjoint
+    n, layers = 9, 2
+    gates = ansatz(n, layers)
+    P = ansatz_params(n, layers, seed=3, count=4)
+    masks, coeffs = zz_chain(n)
+    log("batch adjoint")
+    ev, gr = batch_adjoint(n, gates, P, masks, coeffs, [3 * n], dtype="c128")
+    for k in range(4):
+        ref = oracle.param_shift_gradient(n, gates, P[k], masks, coeffs)
+        assert np.max(np.abs(gr[k] - ref)) < 1e-10
+        assert ev[k] == pytest.approx(oracle.energy(n, gates, P[k], masks, coeffs), abs=1e-12)

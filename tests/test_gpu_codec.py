@@ -56,7 +56,9 @@ def test_edge_arrays(dtype):
         "zeros": np.zeros(N),
         "grid": (rng.integers(-1000, 1000, N) + 1j * rng.integers(-1000, 1000, N)) * step,
         "ties": (rng.integers(-50, 50, N) + 0.5 + 1j * (rng.integers(-50, 50, N) - 0.5)) * step,
-        "near_limit": np.where(np.arange(N) % 2 == 0, 1, -1) * (2 ** 30 - 1) * step + 0j,
+        # largest codes whose values are representable in both float types
+        "near_limit": np.where(np.arange(N) % 2 == 0, 1, -1) * (2 ** 30 - (64 if dtype == np.complex64 else 1))
+        * step + 0j,
         "tiny": np.full(N, 0.49 * step + 0.49j * step),
     }
     dt = "c128" if dtype == np.complex128 else "c64"
