@@ -48,6 +48,8 @@ struct PassGeom {
     uint64_t nontile_mask; // global bits that index tiles
     uint64_t tile_begin;   // first tile of this launch
     uint64_t n_tiles;      // tiles in this launch
+    int32_t max_k;         // widest dense op of the pass (selects the kernel variant)
+    int32_t pad_;
 };
 
 }  // namespace msv

@@ -16,7 +16,7 @@
 
 namespace msv {
 
-template <typename T, int TB, bool LOADC, bool STOREC>
+template <typename T, int TB, bool LOADC, bool STOREC, int KMAX>
 __global__ __launch_bounds__(kThreads) void pass_kernel(PassGeom geo, PassBuffers buf)
 {
     constexpr int TILE = 1 << TB;
@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassGeom geo, PassBuffer
         if (op.type == OP_OBS)
             op_obs<T, TB>(sre, sim, sG, buf.obs_masks, buf.obs_coeffs, buf.obs_terms);
         else
-            apply_op<T, TB>(sre, sim, op, pool + 2 * (int64_t)op.mat, base, geo.n, sph);
+            apply_op<T, TB, KMAX>(sre, sim, op, pool + 2 * (int64_t)op.mat, base, geo.n, sph);
         __syncthreads();
     }
 
@@ -74,20 +74,30 @@ __global__ __launch_bounds__(kThreads) void pass_kernel(PassGeom geo, PassBuffer
     }
 }
 
+template <typename T, int TB, int KMAX>
+static hipError_t launch_k(bool load_c, bool store_c, const PassGeom &geo, const PassBuffers &buf,
+                           hipStream_t stream)
+{
+    const dim3 grid((unsigned)geo.n_tiles), block(kThreads);
+    if (load_c && store_c)
+        hipLaunchKernelGGL((pass_kernel<T, TB, true, true, KMAX>), grid, block, 0, stream, geo, buf);
+    else if (load_c)
+        hipLaunchKernelGGL((pass_kernel<T, TB, true, false, KMAX>), grid, block, 0, stream, geo, buf);
+    else if (store_c)
+        hipLaunchKernelGGL((pass_kernel<T, TB, false, true, KMAX>), grid, block, 0, stream, geo, buf);
+    else
+        hipLaunchKernelGGL((pass_kernel<T, TB, false, false, KMAX>), grid, block, 0, stream, geo, buf);
+    return hipGetLastError();
+}
+
+// Passes whose dense ops are at most 3 qubits wide run a variant compiled
+// without the 4- and 5-qubit paths (fewer registers, higher occupancy).
 template <typename T, int TB>
 static hipError_t launch_tb(bool load_c, bool store_c, const PassGeom &geo, const PassBuffers &buf,
                             hipStream_t stream)
 {
-    const dim3 grid((unsigned)geo.n_tiles), block(kThreads);
-    if (load_c && store_c)
-        hipLaunchKernelGGL((pass_kernel<T, TB, true, true>), grid, block, 0, stream, geo, buf);
-    else if (load_c)
-        hipLaunchKernelGGL((pass_kernel<T, TB, true, false>), grid, block, 0, stream, geo, buf);
-    else if (store_c)
-        hipLaunchKernelGGL((pass_kernel<T, TB, false, true>), grid, block, 0, stream, geo, buf);
-    else
-        hipLaunchKernelGGL((pass_kernel<T, TB, false, false>), grid, block, 0, stream, geo, buf);
-    return hipGetLastError();
+    if (geo.max_k <= 3) return launch_k<T, TB, 3>(load_c, store_c, geo, buf, stream);
+    return launch_k<T, TB, 5>(load_c, store_c, geo, buf, stream);
 }
 
 template <typename T>

@@ -476,6 +476,9 @@ bool lower_passes(const std::vector<Pass> &passes, const PlanOptions &o, std::ve
             ops.push_back(d);
         }
         ok = ok && (int)ps.tile_q.size() == tb && ps.tile_q[0] == 0 && ps.tile_q[5] == 5;
+        g.max_k = 0;
+        for (int i = g.op_begin; i < (int)ops.size(); ++i)
+            if (ops[i].type == OP_DENSE || ops[i].type == OP_MFMA) g.max_k = std::max<int>(g.max_k, ops[i].k);
         geoms.push_back(g);
     }
     return ok;

@@ -65,28 +65,61 @@ __device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, co
 {
     constexpr int NAB = 1 << (TB - 6), NSB = 2 * NAB, NW = kThreads / 64;
     using V2 = typename Cplx<T>::V;
+    const T scale = (T)sc;
     if (!LOADC) {
+        // every load of the wave in flight before the first LDS write
+        constexpr int PER = (NAB + NW - 1) / NW;
         const V2 *a = (const V2 *)amps;
-        const T scale = (T)sc;
-        for (int jb = wave; jb < NAB; jb += NW) {
-            V2 v = a[(sG[jb] << 6) | (uint64_t)lane];
-            if (sc != 1.0) { v.x *= scale; v.y *= scale; }
-            sre[jb * 64 + lane] = v.x;
-            sim[jb * 64 + lane] = v.y;
+        V2 v[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int jb = wave + NW * i;
+            if (jb < NAB) v[i] = a[(sG[jb] << 6) | (uint64_t)lane];
         }
-    } else {
-        const T scale = (T)sc;
-        for (int bt = wave; bt < NSB; bt += NW) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int jb = wave + NW * i;
+            if (jb < NAB) {
+                if (sc != 1.0) { v[i].x *= scale; v[i].y *= scale; }
+                sre[jb * 64 + lane] = v[i].x;
+                sim[jb * 64 + lane] = v[i].y;
+            }
+        }
+        return;
+    }
+    // Compressed: the wave's stream blocks bt = wave + NW * j are decoded in
+    // rounds of up to 32. Lane j fetches block j's width, anchor and payload
+    // offset; then every block's payload word `lane` is loaded; one wait
+    // covers all of them before the bit planes are unpacked.
+    constexpr int BPW = (NSB + NW - 1) / NW;   // blocks per wave (the last wave may have fewer)
+    constexpr int RB = BPW < 32 ? BPW : 32;
+    for (int r0 = 0; r0 < BPW; r0 += RB) {
+        uint32_t wv = 0, ov = 0;
+        int32_t av = 0;
+        if (lane < RB && wave + NW * (r0 + lane) < NSB) {
+            const int bt = wave + NW * (r0 + lane);
             const int jb = bt >> 1, p = bt & 1;
             const uint64_t bi = block_index(in, 2 * sG[jb] + (uint64_t)p);
-            const uint32_t W = in.W[bi];
-            const int32_t A = in.A[bi];
-            uint64_t mine = 0;
-            if (W) {
-                const uint64_t off = in.OFF[bi];
-                if ((uint32_t)lane < W) mine = in.heap[off + lane];
-            }
-            T x = dequantize<T>(unpack_codes(mine, W, A), step);
+            wv = in.W[bi];
+            av = in.A[bi];
+            if (wv) ov = in.OFF[bi];
+        }
+        uint64_t mine[RB];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            const uint32_t W = (uint32_t)__builtin_amdgcn_readlane((int)wv, j);
+            const uint32_t off = (uint32_t)__builtin_amdgcn_readlane((int)ov, j);
+            mine[j] = 0;
+            if ((uint32_t)lane < W) mine[j] = in.heap[(uint64_t)off + lane];
+        }
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+            const int bt = wave + NW * (r0 + j);
+            if (bt >= NSB) break;
+            const int jb = bt >> 1, p = bt & 1;
+            const uint32_t W = (uint32_t)__builtin_amdgcn_readlane((int)wv, j);
+            const int32_t A = __builtin_amdgcn_readlane(av, j);
+            T x = dequantize<T>(unpack_codes(mine[j], W, A), step);
             if (sc != 1.0) x *= scale;
             (p ? sim : sre)[jb * 64 + lane] = x;
         }
@@ -121,7 +154,7 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
     }
     bool bad = false;
     // E1: codes, residuals, widths; the zigzag residual replaces the value in LDS
-    for (int bt = wave; bt < NSB; bt += NW) {
+    for (int bt = wave; bt < NSB; bt += NW) {   // block j of the wave: bt = wave + NW j
         const int jb = bt >> 1, p = bt & 1;
         T *plane = p ? sim : sre;
         const T x = plane[jb * 64 + lane];
@@ -160,8 +193,12 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
         }
     }
     __syncthreads();
-    // E3: bit planes into this tile's heap slot
-    for (int bt = wave; bt < NSB; bt += NW) {
+    // E3: bit planes into this tile's heap slot; then lane j of the wave
+    // writes the width, anchor and offset of the wave's block j
+    constexpr int BPW = (NSB + NW - 1) / NW;
+    for (int j = 0; j < BPW; ++j) {
+        const int bt = wave + NW * j;
+        if (bt >= NSB) break;
         const int jb = bt >> 1, p = bt & 1;
         const T *plane = p ? sim : sre;
         const uint32_t u = reinterpret_cast<const uint32_t *>(plane)[(jb * 64 + lane) * VPT];
@@ -169,11 +206,16 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
         const uint64_t mine = pack_planes(u, W);
         const uint64_t off = slot + sOff[bt];
         if ((uint32_t)lane < W) out.heap[off + lane] = mine;
-        if (lane == 0) {
+    }
+    for (int j0 = 0; j0 < BPW; j0 += 64) {
+        const int j = j0 + lane;
+        if (j < BPW && wave + NW * j < NSB) {
+            const int bt = wave + NW * j;
+            const int jb = bt >> 1, p = bt & 1;
             const uint64_t bi = block_index(out, 2 * sG[jb] + (uint64_t)p);
-            out.W[bi] = (uint8_t)W;
+            out.W[bi] = (uint8_t)sW[bt];
             out.A[bi] = sA[bt];
-            out.OFF[bi] = (uint32_t)off;
+            out.OFF[bi] = (uint32_t)(slot + sOff[bt]);
         }
     }
     return sOff[NSB - 1] + sW[NSB - 1];
@@ -365,7 +407,8 @@ __device__ __forceinline__ void op_obs(T *__restrict__ sre, T *__restrict__ sim,
 }
 
 // One op (dense, diagonal, phase) on one tile. Ends without a barrier.
-template <typename T, int TB>
+// KMAX bounds the dense width compiled in (register use grows with it).
+template <typename T, int TB, int KMAX = 5>
 __device__ __forceinline__ void apply_op(T *sre, T *sim, const OpDesc &op, const T *M, uint64_t base, int n,
                                          T *sph)
 {
@@ -374,9 +417,9 @@ __device__ __forceinline__ void apply_op(T *sre, T *sim, const OpDesc &op, const
             switch (op.k) {
             case 1: op_dense<T, TB, 1>(sre, sim, op, M); break;
             case 2: op_dense<T, TB, 2>(sre, sim, op, M); break;
-            case 3: op_dense<T, TB, 3>(sre, sim, op, M); break;
-            case 4: op_dense<T, TB, 4>(sre, sim, op, M); break;
-            default: op_dense<T, TB, 5>(sre, sim, op, M); break;
+            case 3: op_dense<T, TB, (KMAX >= 3 ? 3 : 1)>(sre, sim, op, M); break;
+            case 4: op_dense<T, TB, (KMAX >= 4 ? 4 : 1)>(sre, sim, op, M); break;
+            default: op_dense<T, TB, (KMAX >= 5 ? 5 : 1)>(sre, sim, op, M); break;
             }
         }
     } else if (op.type == OP_DIAG) {
