@@ -136,6 +136,8 @@ int msv_set_fusion(msv_sim *sim, int k_max, int mma_precision);
  *   "mfma_min_k"   smallest fused width run on matrix cores (3..6; 6 = never)
  *   "batch_chunks" host store: chunks per streamed batch (0 = automatic)
  *   "time_passes"  1 = time every pass kernel with events (msv_stats.t_pass)
+ *   "lookahead"    gates the planner scans past a deferred gate to pull
+ *                  commuting gates into the current pass (default 64, 0 = none)
  *   "autotune"     1 = choose fusion width and tile size per msv_apply from a
  *                  cost model calibrated once per process on the GPU */
 int msv_set_option(msv_sim *sim, const char *key, double value);
@@ -184,6 +186,22 @@ int msv_get_stats(msv_sim *sim, msv_stats *out);
  * msv_codec_encode). *out_bytes receives the size; cap may be 0 to query. */
 int msv_export_chunk(msv_sim *sim, uint64_t chunk, void *host_out, size_t cap,
                      size_t *out_bytes);
+
+/* ---- planning (host only, no device work) -----------------------------------
+ * The plan msv_apply would run: passes (stages) and the fused kernel-level ops
+ * of each, for inspection and tests. Written to buf (doubles) as one record
+ * per op, in execution order:
+ *   [pass, type (0 dense, 1 diagonal, 3 controlled phase), k, q0..q4 (-1
+ *    unused), ctrl_mask, tile_mask, hub, len, data[len]]
+ * dense: data = 2^k x 2^k complex matrix (row-major, re/im) on (q0..q_{k-1}),
+ *        applied only where every bit of ctrl_mask is 1;
+ * diagonal: data = 2^k complex entries on (q0..q_{k-1});
+ * controlled phase: data = [G re, G im, mu[n], lam[n]], the factor
+ *        G e^{i sum mu_q b_q} (b_hub ? e^{i sum lam_q b_q} : 1).
+ * tile_mask holds the pass's tile qubits. *used receives the doubles needed
+ * (call with cap 0 to size buf). */
+int msv_plan_export(int n_qubits, const msv_gate *gates, size_t n_gates, int log2_tile, int k_max,
+                    int lookahead, double *buf, size_t cap, size_t *used, uint64_t *n_passes);
 
 /* ---- codec on its own ---------------------------------------------------------
  * Format "MSVC" v1 for a chunk of C = 2^log2_chunk complex values:

@@ -58,7 +58,7 @@ EXPORTS = (
     "msv_set_stream", "msv_init_basis", "msv_init_state", "msv_apply", "msv_prob_one",
     "msv_expect_z", "msv_get_amplitudes", "msv_fidelity", "msv_get_stats", "msv_export_chunk",
     "msv_codec_encode", "msv_codec_decode", "msv_codec_bound", "msv_adjoint", "msv_batch_run",
-    "msv_batch_adjoint",
+    "msv_batch_adjoint", "msv_plan_export",
 )
 
 _lib = None
@@ -117,6 +117,8 @@ def load():
                            P, C.POINTER(Stats)], C.c_int),
         "msv_batch_adjoint": ([C.POINTER(Circuit), P, C.c_size_t, C.c_size_t, P, P, C.c_size_t, P,
                                C.c_size_t, C.c_int, C.c_double, P, P], C.c_int),
+        "msv_plan_export": ([C.c_int, C.POINTER(Gate), C.c_size_t, C.c_int, C.c_int, C.c_int, P, C.c_size_t,
+                             C.POINTER(C.c_size_t), C.POINTER(C.c_uint64)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)

@@ -308,6 +308,7 @@ extern "C" int msv_adjoint(msv_sim *s, const msv_gate *gates, size_t n_gates, co
     o.tb = std::min(choose_tile_bits(s), 12);
     o.k_max = s->k_max;
     o.mfma_min_k = s->mfma_min_k;
+    o.lookahead = s->lookahead;
     const uint64_t stride = 1ull << (s->n - o.tb);
     Scratch w;
     struct Free {

@@ -409,6 +409,9 @@ int msv_set_option(msv_sim *s, const char *key, double v)
     } else if (!strcmp(key, "mfma_min_k")) {
         if (v != iv || iv < 3 || iv > 6) return fail(s, MSV_E_ARG, "mfma_min_k in 3..6");
         s->mfma_min_k = iv;
+    } else if (!strcmp(key, "lookahead")) {
+        if (v != iv || iv < 0 || iv > 4096) return fail(s, MSV_E_ARG, "lookahead in 0..4096");
+        s->lookahead = iv;
     } else if (!strcmp(key, "autotune")) {
         s->autotune = v != 0.0;
     } else if (!strcmp(key, "time_passes")) {
@@ -580,6 +583,7 @@ int msv_apply(msv_sim *s, const msv_gate *gates, size_t n_gates)
         o.tb = choose_tile_bits(s);
         o.k_max = s->k_max;
         o.mfma_min_k = s->mfma_min_k;
+        o.lookahead = s->lookahead;
         std::vector<Pass> passes;
         if (s->autotune && s->compressed()) {
             int k = o.k_max, tb = o.tb;
@@ -797,6 +801,60 @@ int msv_get_stats(msv_sim *s, msv_stats *out)
         r.ratio = 1.0;
     }
     *out = r;
+    return MSV_OK;
+}
+
+int msv_plan_export(int n, const msv_gate *gates, size_t n_gates, int log2_tile, int k_max, int lookahead,
+                    double *buf, size_t cap, size_t *used, uint64_t *n_passes)
+{
+    if (n < 6 || n > 40 || (n_gates && !gates) || !used || !n_passes || k_max < 1 || k_max > kMaxFuse ||
+        log2_tile < kMinTileBits || log2_tile > kMaxTileBits || lookahead < 0)
+        return fail(nullptr, MSV_E_ARG, "bad plan arguments");
+    std::vector<Prim> prims(n_gates);
+    std::string err;
+    for (size_t i = 0; i < n_gates; ++i) {
+        int st = gate_to_prim(gates[i], n, false, prims[i], err);
+        if (st) return fail(nullptr, st, "gate %zu: %s", i, err.c_str());
+        prims[i].gate = i;
+    }
+    PlanOptions o;
+    o.n = n;
+    o.tb = std::min(log2_tile, n);
+    o.k_max = k_max;
+    o.lookahead = lookahead;
+    std::vector<Pass> passes = plan_passes(prims, o);
+    std::vector<double> out;
+    for (size_t p = 0; p < passes.size(); ++p) {
+        uint64_t tmask = 0;
+        for (int q : passes[p].tile_q) tmask |= 1ull << q;
+        for (const HostOp &h : passes[p].ops) {
+            out.push_back((double)p);
+            out.push_back((double)h.type);
+            out.push_back((double)h.q.size());
+            for (int m = 0; m < 5; ++m) out.push_back(m < (int)h.q.size() ? (double)h.q[m] : -1.0);
+            out.push_back((double)h.ctrl_mask);
+            out.push_back((double)tmask);
+            out.push_back((double)h.hub);
+            std::vector<double> d;
+            if (h.type == OP_PHASE) {
+                d.push_back(h.global.real());
+                d.push_back(h.global.imag());
+                d.insert(d.end(), h.mu.begin(), h.mu.end());
+                d.insert(d.end(), h.lam.begin(), h.lam.end());
+            } else {
+                for (const cd &v : h.m) {
+                    d.push_back(v.real());
+                    d.push_back(v.imag());
+                }
+            }
+            out.push_back((double)d.size());
+            out.insert(out.end(), d.begin(), d.end());
+        }
+    }
+    *used = out.size();
+    *n_passes = passes.size();
+    if (buf && cap >= out.size()) std::copy(out.begin(), out.end(), buf);
+    else if (buf) return fail(nullptr, MSV_E_ARG, "plan buffer too small");
     return MSV_OK;
 }
 

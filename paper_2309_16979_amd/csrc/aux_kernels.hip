@@ -67,28 +67,91 @@ hipError_t launch_init_basis_block(bool is_double, BlockStore st, uint64_t index
 
 constexpr int kRedGroups = 2048;
 
+// Amplitude blocks G = first + k, k = blockIdx.x * NW + wave + stride * j,
+// decoded both planes at a time in rounds of up to 16 per wave: lane 2a + p
+// fetches the metadata of round block a, plane p, then every block's payload
+// word `lane` is loaded before one wait. f(G, xr, xi) runs per decoded block.
+template <typename T, bool COMP, typename F>
+static __device__ __forceinline__ void for_amp_blocks(const void *amps, const BlockStore &st, double step,
+                                                      uint64_t first, uint64_t nab, int wave, int lane, F &&f)
+{
+    using V2 = typename Vec2<T>::V;
+    constexpr int NW = kThreads / 64;
+    constexpr int RA = 16;
+    const uint64_t stride = (uint64_t)gridDim.x * NW;
+    for (uint64_t k0 = (uint64_t)blockIdx.x * NW + wave; k0 < nab; k0 += stride * RA) {
+        if (!COMP) {
+            V2 v[RA];
+#pragma unroll
+            for (int a = 0; a < RA; ++a) {
+                const uint64_t k = k0 + stride * a;
+                if (k < nab) v[a] = ((const V2 *)amps)[((first + k) << 6) | (uint64_t)lane];
+            }
+#pragma unroll
+            for (int a = 0; a < RA; ++a) {
+                const uint64_t k = k0 + stride * a;
+                if (k < nab) f(first + k, (double)v[a].x, (double)v[a].y);
+            }
+            continue;
+        }
+        uint32_t wv = 0, ov = 0;
+        int32_t av = 0;
+        {
+            const uint64_t k = k0 + stride * (uint64_t)(lane >> 1);
+            if (lane < 2 * RA && k < nab) {
+                const uint64_t bi = bidx(st, 2 * (first + k) + (uint64_t)(lane & 1));
+                wv = st.W[bi];
+                av = st.A[bi];
+                if (wv) ov = st.OFF[bi];
+            }
+        }
+        uint64_t mine[2 * RA];
+#pragma unroll
+        for (int j = 0; j < 2 * RA; ++j) {
+            const uint32_t W = (uint32_t)__builtin_amdgcn_readlane((int)wv, j);
+            const uint32_t off = (uint32_t)__builtin_amdgcn_readlane((int)ov, j);
+            mine[j] = 0;
+            if ((uint32_t)lane < W) mine[j] = st.heap[(uint64_t)off + lane];
+        }
+#pragma unroll
+        for (int a = 0; a < RA; ++a) {
+            const uint64_t k = k0 + stride * a;
+            if (k >= nab) break;
+            int32_t qr, qi;
+            unpack_codes2(mine[2 * a], (uint32_t)__builtin_amdgcn_readlane((int)wv, 2 * a),
+                          __builtin_amdgcn_readlane(av, 2 * a), mine[2 * a + 1],
+                          (uint32_t)__builtin_amdgcn_readlane((int)wv, 2 * a + 1),
+                          __builtin_amdgcn_readlane(av, 2 * a + 1), qr, qi);
+            f(first + k, (double)dequantize<T>(qr, step), (double)dequantize<T>(qi, step));
+        }
+    }
+}
+
+constexpr int kFastTerms = 32;
+
 template <typename T, bool COMP>
 __global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, BlockStore st, double step,
                                                           ReduceArgs a)
 {
-    using V2 = typename Vec2<T>::V;
     constexpr int NW = kThreads / 64;
     __shared__ double sacc[4][NW];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t nab = a.amp_count >> 6, first = a.amp_begin >> 6;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (uint64_t k = (uint64_t)blockIdx.x * NW + wave; k < nab; k += (uint64_t)gridDim.x * NW) {
-        const uint64_t G = first + k;
-        double xr, xi;
-        if (COMP) {
-            xr = (double)decode_one<T>(st, 2 * G, step);
-            xi = (double)decode_one<T>(st, 2 * G + 1, step);
-        } else {
-            const V2 v = ((const V2 *)amps)[(G << 6) | (uint64_t)lane];
-            xr = v.x;
-            xi = v.y;
-        }
+    // Z-strings: the sign of term t at index i = (G << 6) | lane factors into a
+    // lane part, folded into tl[t] = c_t (-1)^popcount(lane & m_t) once, and a
+    // block part applied per block.
+    const bool fast = a.kind == RED_EXPZ && a.n_terms <= kFastTerms;
+    double tl[kFastTerms];
+    if (fast) {
+#pragma unroll
+        for (int t = 0; t < kFastTerms; ++t)
+            tl[t] = t < a.n_terms ? ((__popc((uint32_t)(a.masks[t] & 63u) & (uint32_t)lane) & 1) ? -a.coeffs[t]
+                                                                                                 : a.coeffs[t])
+                                  : 0.0;
+    }
+    for_amp_blocks<T, COMP>(amps, st, step, first, nab, wave, lane, [&](uint64_t G, double xr, double xi) {
         xr *= a.scale;
         xi *= a.scale;
         const uint64_t i = (G << 6) | (uint64_t)lane;
@@ -98,8 +161,17 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, Bloc
             if ((i >> a.qubit) & 1ull) acc[1] += p;
         } else if (a.kind == RED_EXPZ) {
             double v = 0.0;
-            for (int t = 0; t < a.n_terms; ++t)
-                v += (__popcll(i & a.masks[t]) & 1) ? -a.coeffs[t] : a.coeffs[t];
+            if (fast) {
+#pragma unroll
+                for (int t = 0; t < kFastTerms; ++t) {
+                    if (t >= a.n_terms) break;
+                    const double sg = (__popcll((G << 6) & a.masks[t]) & 1) ? -1.0 : 1.0;
+                    v = __builtin_fma(sg, tl[t], v);
+                }
+            } else {
+                for (int t = 0; t < a.n_terms; ++t)
+                    v += (__popcll(i & a.masks[t]) & 1) ? -a.coeffs[t] : a.coeffs[t];
+            }
             acc[1] += p * v;
         } else if (a.kind == RED_OVERLAP) {
             const uint64_t r = i - a.amp_begin;
@@ -108,7 +180,7 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, Bloc
             acc[2] += rr * xi - ri * xr;   // Im(conj(ref) psi)
             acc[3] += rr * rr + ri * ri;
         }
-    }
+    });
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const double s = wave_sum_f64(acc[j]);
@@ -208,17 +280,15 @@ __global__ __launch_bounds__(kThreads) void decode_range_kernel(BlockStore st, d
                                                                 uint64_t first, uint64_t nab, void *out)
 {
     using V2 = typename Vec2<T>::V;
-    constexpr int NW = kThreads / 64;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (uint64_t k = (uint64_t)blockIdx.x * NW + wave; k < nab; k += (uint64_t)gridDim.x * NW) {
-        const uint64_t G = first + k;
+    for_amp_blocks<T, true>(nullptr, st, step, first, nab, wave, lane, [&](uint64_t G, double xr, double xi) {
         V2 v;
-        v.x = decode_one<T>(st, 2 * G, step);
-        v.y = decode_one<T>(st, 2 * G + 1, step);
+        v.x = (T)xr;
+        v.y = (T)xi;
         if (scale != 1.0) { v.x = (T)(v.x * (T)scale); v.y = (T)(v.y * (T)scale); }
-        ((V2 *)out)[(k << 6) | (uint64_t)lane] = v;
-    }
+        ((V2 *)out)[((G - first) << 6) | (uint64_t)lane] = v;
+    });
 }
 
 hipError_t launch_decode_range(bool is_double, BlockStore st, double step, double scale, uint64_t amp_begin,

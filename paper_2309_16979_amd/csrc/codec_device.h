@@ -116,6 +116,71 @@ __device__ __forceinline__ int32_t unpack_codes(uint64_t mine, uint32_t W, int32
     return (int32_t)((uint32_t)A + wave_inclusive_sum(d));
 }
 
+// Two independent inclusive prefix sums, interleaved so that each DPP step of
+// one chain fills the other's hazard slots.
+__device__ __forceinline__ void wave_inclusive_sum2(uint32_t &x, uint32_t &y)
+{
+    x += dpp_u32<0x111, 0xf, 0xf, true>(x);
+    y += dpp_u32<0x111, 0xf, 0xf, true>(y);
+    x += dpp_u32<0x112, 0xf, 0xf, true>(x);
+    y += dpp_u32<0x112, 0xf, 0xf, true>(y);
+    x += dpp_u32<0x114, 0xf, 0xf, true>(x);
+    y += dpp_u32<0x114, 0xf, 0xf, true>(y);
+    x += dpp_u32<0x118, 0xf, 0xf, true>(x);
+    y += dpp_u32<0x118, 0xf, 0xf, true>(y);
+    x += dpp_u32<0x142, 0xa, 0xf, false>(x);
+    y += dpp_u32<0x142, 0xa, 0xf, false>(y);
+    x += dpp_u32<0x143, 0xc, 0xf, false>(x);
+    y += dpp_u32<0x143, 0xc, 0xf, false>(y);
+}
+
+// Widths of two blocks (OR reductions interleaved).
+__device__ __forceinline__ void block_width2(uint32_t u, uint32_t v, uint32_t &wu, uint32_t &wv)
+{
+    u |= dpp_u32<0x111, 0xf, 0xf, true>(u);
+    v |= dpp_u32<0x111, 0xf, 0xf, true>(v);
+    u |= dpp_u32<0x112, 0xf, 0xf, true>(u);
+    v |= dpp_u32<0x112, 0xf, 0xf, true>(v);
+    u |= dpp_u32<0x114, 0xf, 0xf, true>(u);
+    v |= dpp_u32<0x114, 0xf, 0xf, true>(v);
+    u |= dpp_u32<0x118, 0xf, 0xf, true>(u);
+    v |= dpp_u32<0x118, 0xf, 0xf, true>(v);
+    u |= dpp_u32<0x142, 0xa, 0xf, false>(u);
+    v |= dpp_u32<0x142, 0xa, 0xf, false>(v);
+    u |= dpp_u32<0x143, 0xc, 0xf, false>(u);
+    v |= dpp_u32<0x143, 0xc, 0xf, false>(v);
+    const uint32_t ou = (uint32_t)__builtin_amdgcn_readlane((int)u, 63);
+    const uint32_t ov = (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+    wu = ou ? 32u - (uint32_t)__builtin_clz(ou) : 0u;
+    wv = ov ? 32u - (uint32_t)__builtin_clz(ov) : 0u;
+}
+
+// Codes of two blocks (the re and im planes of one amplitude block). Lane k
+// holds word k of each block in mr / mi and 0 for k at or beyond its width,
+// so both unpack in one loop up to the larger width.
+__device__ __forceinline__ void unpack_codes2(uint64_t mr, uint32_t Wr, int32_t Ar, uint64_t mi, uint32_t Wi,
+                                              int32_t Ai, int32_t &qr, int32_t &qi)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t sh = lane & 31u;
+    const bool hi = lane >= 32u;
+    const uint32_t Wm = Wr > Wi ? Wr : Wi;
+    uint32_t ur = 0, ui = 0;
+    for (uint32_t k = 0; k < Wm; ++k) {
+        const uint32_t r_lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mr, (int)k);
+        const uint32_t r_hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mr >> 32), (int)k);
+        const uint32_t i_lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mi, (int)k);
+        const uint32_t i_hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mi >> 32), (int)k);
+        ur |= (((hi ? r_hi : r_lo) >> sh) & 1u) << k;
+        ui |= (((hi ? i_hi : i_lo) >> sh) & 1u) << k;
+    }
+    uint32_t dr = (ur >> 1) ^ (0u - (ur & 1u));
+    uint32_t di = (ui >> 1) ^ (0u - (ui & 1u));
+    if (Wm) wave_inclusive_sum2(dr, di);
+    qr = (int32_t)((uint32_t)Ar + dr);
+    qi = (int32_t)((uint32_t)Ai + di);
+}
+
 // FP64 sum over the 64 lanes, returned to every lane (butterfly: the same
 // order on every call, so the result is reproducible).
 __device__ __forceinline__ double wave_sum_f64(double x)

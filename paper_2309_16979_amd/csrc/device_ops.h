@@ -36,6 +36,8 @@ struct OpDesc {
     int32_t ctrl_q;        // PHASE: global control qubit, -1 = none
     int32_t slot;          // GRAD: gradient slot
     int32_t diag;          // GRAD: 1 = A is diagonal (table in the pool, qubits in gq/pos)
+    int32_t real;          // DENSE: 1 = every matrix entry is real (imaginary parts ignored)
+    int32_t pad_;
 };
 
 // Geometry and buffers of one pass launch.

@@ -386,6 +386,7 @@ int apply_host_store(msv_sim *s, const std::vector<Prim> &prims, size_t n_gates)
     o.tb = choose_tile_bits(s);
     o.k_max = s->k_max;
     o.mfma_min_k = s->mfma_min_k;
+    o.lookahead = s->lookahead;
     std::vector<Pass> passes = plan_passes(prims, o);
     std::vector<OpDesc> ops;
     std::vector<PassGeom> geoms;

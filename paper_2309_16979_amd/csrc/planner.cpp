@@ -334,36 +334,95 @@ struct Fuser {
 
 }  // namespace
 
+namespace {
+
+// Qubits a prim acts on non-trivially as a dense map (its targets), and all
+// qubits it reads (targets and control).
+std::vector<int> support(const Prim &p)
+{
+    std::vector<int> s = p.q;
+    if (p.ctrl >= 0) s.push_back(p.ctrl);
+    return s;
+}
+
+bool disjoint(const std::vector<int> &a, const std::vector<int> &b)
+{
+    for (int x : a)
+        if (std::find(b.begin(), b.end(), x) != b.end()) return false;
+    return true;
+}
+
+// Sufficient conditions for two gates to commute: disjoint supports; both
+// diagonal; or one diagonal acting only on qubits the other does not
+// transform (a control, or a qubit it does not touch).
+bool commute(const Prim &a, const Prim &b)
+{
+    if (a.probe || b.probe || a.obs || b.obs) return false;
+    if (disjoint(support(a), support(b))) return true;
+    if (a.diag && b.diag) return true;
+    if (a.diag) return disjoint(a.q, b.q);
+    if (b.diag) return disjoint(b.q, a.q);
+    return false;
+}
+
+}  // namespace
+
 std::vector<Pass> plan_passes(const std::vector<Prim> &prims, const PlanOptions &o)
 {
     std::vector<Pass> passes;
     const int tb = o.tb;
-    size_t i = 0;
-    while (i < prims.size()) {
+    // Gates not yet placed, in list order. Each pass takes every gate that
+    // fits the tile and commutes with all gates deferred before it in this
+    // pass, scanning a bounded window ahead of the first deferred gate.
+    std::vector<size_t> rest(prims.size());
+    for (size_t i = 0; i < prims.size(); ++i) rest[i] = i;
+    const size_t window = (size_t)std::max(0, o.lookahead);
+    while (!rest.empty()) {
         std::vector<int> L = {0, 1, 2, 3, 4, 5};
         L.resize(std::min(6, o.n));
-        size_t j = i;
-        for (; j < prims.size(); ++j) {
-            const Prim &p = prims[j];
-            if (p.diag || p.obs) continue;
-            std::vector<int> U = unite(L, p.q);
-            if ((int)U.size() > tb) break;
-            L = U;
+        std::vector<size_t> take, defer;
+        size_t scanned_after_defer = 0;
+        size_t pos = 0;
+        for (; pos < rest.size(); ++pos) {
+            const Prim &p = prims[rest[pos]];
+            if (!defer.empty() && (p.probe || p.obs || ++scanned_after_defer > window)) break;
+            bool fits = true;
+            std::vector<int> U = L;
+            if (!(p.diag || p.obs || p.probe) || (p.probe && !p.diag)) {
+                U = unite(L, p.q);
+                fits = (int)U.size() <= tb;
+            }
+            bool ok = fits;
+            for (size_t d : defer)
+                if (ok && !commute(p, prims[d])) ok = false;
+            if (ok) {
+                take.push_back(rest[pos]);
+                L = U;
+            } else {
+                defer.push_back(rest[pos]);
+            }
         }
+        if (take.empty()) {   // cannot happen for tb >= 8; keep progress regardless
+            take.push_back(rest[0]);
+            defer.erase(defer.begin());
+            L = unite(L, prims[rest[0]].q);
+        }
+        std::vector<size_t> next = defer;
+        next.insert(next.end(), rest.begin() + pos, rest.end());
+        rest.swap(next);
         // fill the tile with the lowest remaining qubits
         for (int q = 0; (int)L.size() < tb && q < o.n; ++q)
             if (std::find(L.begin(), L.end(), q) == L.end()) L.push_back(q);
         std::sort(L.begin(), L.end());
         Pass ps;
         ps.tile_q = L;
-        ps.gate_begin = prims[i].gate;
-        ps.gate_end = prims[j - 1].gate + 1;
+        ps.gate_begin = prims[take.front()].gate;
+        ps.gate_end = prims[take.back()].gate + 1;
         Fuser f(o, ps.tile_q);
-        for (size_t k = i; k < j; ++k) f.add(prims[k]);
+        for (size_t k : take) f.add(prims[k]);
         f.flush();
         ps.ops = f.out;
         passes.push_back(ps);
-        i = j;
     }
     return passes;
 }
@@ -406,6 +465,7 @@ bool lower_passes(const std::vector<Pass> &passes, const PlanOptions &o, std::ve
             d.ctrl_q = -1;
             d.slot = -1;
             d.diag = 0;
+            d.real = 0;
             for (int m = 0; m < 5; ++m) { d.pos[m] = -1; d.gq[m] = -1; }
             if (h.type == OP_DENSE) {
                 d.k = (int32_t)h.q.size();
@@ -416,6 +476,9 @@ bool lower_passes(const std::vector<Pass> &passes, const PlanOptions &o, std::ve
                     ok = ok && d.pos[m] >= 0;
                 }
                 ok = ok && (h.ctrl_mask & tmask) == 0;
+                d.real = 1;
+                for (const cd &v : h.m)
+                    if (v.imag() != 0.0) d.real = 0;
                 d.ctrl_fixed = h.ctrl_mask;
                 for (const cd &v : h.m) push(v);
             } else if (h.type == OP_GRAD) {

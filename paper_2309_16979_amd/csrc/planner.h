@@ -58,6 +58,7 @@ struct PlanOptions {
     int tb = 12;
     int k_max = 2;
     int mfma_min_k = 6;       // dense ops with k >= this run on matrix cores
+    int lookahead = 64;       // gates scanned past the first deferred one (0 = strict order)
 };
 
 // Canonicalise one ABI gate (inverse = apply U^dagger). Returns MSV_OK or an

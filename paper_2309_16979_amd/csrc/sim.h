@@ -79,6 +79,7 @@ struct msv_sim {
     int batch_chunks = 0;
     int time_passes = 0;
     int autotune = 0;
+    int lookahead = 64;
     int tuned_k = 0, tuned_tb = 0;   // last autotuner choice
     void *(*alloc)(size_t, void *) = nullptr;
     void (*dealloc)(void *, void *) = nullptr;

@@ -87,41 +87,47 @@ __device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, co
         }
         return;
     }
-    // Compressed: the wave's stream blocks bt = wave + NW * j are decoded in
-    // rounds of up to 32. Lane j fetches block j's width, anchor and payload
-    // offset; then every block's payload word `lane` is loaded; one wait
-    // covers all of them before the bit planes are unpacked.
-    constexpr int BPW = (NSB + NW - 1) / NW;   // blocks per wave (the last wave may have fewer)
-    constexpr int RB = BPW < 32 ? BPW : 32;
-    for (int r0 = 0; r0 < BPW; r0 += RB) {
+    // Compressed: the wave decodes amplitude blocks jb = wave + NW * a, both
+    // planes together, in rounds of up to 16. Lane j < 32 fetches the width,
+    // anchor and payload offset of amplitude block a = r0 + j / 2, plane j & 1;
+    // then every block's payload word `lane` is loaded, and one wait covers
+    // all of them before the bit planes are unpacked.
+    constexpr int APW = (NAB + NW - 1) / NW;   // amplitude blocks per wave
+    constexpr int RA = APW < 16 ? APW : 16;
+    for (int r0 = 0; r0 < APW; r0 += RA) {
         uint32_t wv = 0, ov = 0;
         int32_t av = 0;
-        if (lane < RB && wave + NW * (r0 + lane) < NSB) {
-            const int bt = wave + NW * (r0 + lane);
-            const int jb = bt >> 1, p = bt & 1;
-            const uint64_t bi = block_index(in, 2 * sG[jb] + (uint64_t)p);
-            wv = in.W[bi];
-            av = in.A[bi];
-            if (wv) ov = in.OFF[bi];
+        {
+            const int a = r0 + (lane >> 1);
+            const int jb = wave + NW * a;
+            if (lane < 2 * RA && a < APW && jb < NAB) {
+                const uint64_t bi = block_index(in, 2 * sG[jb] + (uint64_t)(lane & 1));
+                wv = in.W[bi];
+                av = in.A[bi];
+                if (wv) ov = in.OFF[bi];
+            }
         }
-        uint64_t mine[RB];
+        uint64_t mine[2 * RA];
 #pragma unroll
-        for (int j = 0; j < RB; ++j) {
+        for (int j = 0; j < 2 * RA; ++j) {
             const uint32_t W = (uint32_t)__builtin_amdgcn_readlane((int)wv, j);
             const uint32_t off = (uint32_t)__builtin_amdgcn_readlane((int)ov, j);
             mine[j] = 0;
             if ((uint32_t)lane < W) mine[j] = in.heap[(uint64_t)off + lane];
         }
 #pragma unroll
-        for (int j = 0; j < RB; ++j) {
-            const int bt = wave + NW * (r0 + j);
-            if (bt >= NSB) break;
-            const int jb = bt >> 1, p = bt & 1;
-            const uint32_t W = (uint32_t)__builtin_amdgcn_readlane((int)wv, j);
-            const int32_t A = __builtin_amdgcn_readlane(av, j);
-            T x = dequantize<T>(unpack_codes(mine[j], W, A), step);
-            if (sc != 1.0) x *= scale;
-            (p ? sim : sre)[jb * 64 + lane] = x;
+        for (int a = 0; a < RA; ++a) {
+            const int jb = wave + NW * (r0 + a);
+            if (r0 + a >= APW || jb >= NAB) break;
+            int32_t qr, qi;
+            unpack_codes2(mine[2 * a], (uint32_t)__builtin_amdgcn_readlane((int)wv, 2 * a),
+                          __builtin_amdgcn_readlane(av, 2 * a), mine[2 * a + 1],
+                          (uint32_t)__builtin_amdgcn_readlane((int)wv, 2 * a + 1),
+                          __builtin_amdgcn_readlane(av, 2 * a + 1), qr, qi);
+            T xr = dequantize<T>(qr, step), xi = dequantize<T>(qi, step);
+            if (sc != 1.0) { xr *= scale; xi *= scale; }
+            sre[jb * 64 + lane] = xr;
+            sim[jb * 64 + lane] = xi;
         }
     }
 }
@@ -153,23 +159,33 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
         return 0;
     }
     bool bad = false;
-    // E1: codes, residuals, widths; the zigzag residual replaces the value in LDS
-    for (int bt = wave; bt < NSB; bt += NW) {   // block j of the wave: bt = wave + NW j
-        const int jb = bt >> 1, p = bt & 1;
-        T *plane = p ? sim : sre;
-        const T x = plane[jb * 64 + lane];
-        const double xd = (double)x;
-        nrm += xd * xd;
-        const int32_t q = quantize<T>(x, inv_step, bad);
+    // E1 (per amplitude block, both planes): codes, residuals, widths; the
+    // zigzag residuals replace the values in LDS
+    for (int jb = wave; jb < NAB; jb += NW) {
+        const int l = jb * 64 + lane;
+        const T xr = sre[l], xi = sim[l];
+        const double dr = (double)xr, di = (double)xi;
+        nrm += dr * dr + di * di;
+        const int32_t qr = quantize<T>(xr, inv_step, bad);
+        const int32_t qi = quantize<T>(xi, inv_step, bad);
         if (check) {
-            const T xr = dequantize<T>(q, step);
-            err = fmax(err, __builtin_fabs(xd - (double)xr));
+            const T yr = dequantize<T>(qr, step), yi = dequantize<T>(qi, step);
+            err = fmax(err, fmax(__builtin_fabs(dr - (double)yr), __builtin_fabs(di - (double)yi)));
         }
-        const uint32_t u = residual_zigzag(q);
-        const uint32_t W = block_width(u);
-        const int32_t A = __builtin_amdgcn_readlane(q, 0);
-        reinterpret_cast<uint32_t *>(plane)[(jb * 64 + lane) * VPT] = u;
-        if (lane == 0) { sW[bt] = W; sA[bt] = A; }
+        const uint32_t ur = residual_zigzag(qr);
+        const uint32_t ui = residual_zigzag(qi);
+        uint32_t Wr, Wi;
+        block_width2(ur, ui, Wr, Wi);
+        const int32_t Ar = __builtin_amdgcn_readlane(qr, 0);
+        const int32_t Ai = __builtin_amdgcn_readlane(qi, 0);
+        reinterpret_cast<uint32_t *>(sre)[l * VPT] = ur;
+        reinterpret_cast<uint32_t *>(sim)[l * VPT] = ui;
+        if (lane == 0) {
+            sW[2 * jb] = Wr;
+            sW[2 * jb + 1] = Wi;
+            sA[2 * jb] = Ar;
+            sA[2 * jb + 1] = Ai;
+        }
     }
     if (bad) atomicOr(flags, 1u);
     __syncthreads();
@@ -193,26 +209,25 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
         }
     }
     __syncthreads();
-    // E3: bit planes into this tile's heap slot; then lane j of the wave
-    // writes the width, anchor and offset of the wave's block j
-    constexpr int BPW = (NSB + NW - 1) / NW;
-    for (int j = 0; j < BPW; ++j) {
-        const int bt = wave + NW * j;
-        if (bt >= NSB) break;
-        const int jb = bt >> 1, p = bt & 1;
-        const T *plane = p ? sim : sre;
-        const uint32_t u = reinterpret_cast<const uint32_t *>(plane)[(jb * 64 + lane) * VPT];
-        const uint32_t W = sW[bt];
-        const uint64_t mine = pack_planes(u, W);
-        const uint64_t off = slot + sOff[bt];
-        if ((uint32_t)lane < W) out.heap[off + lane] = mine;
+    // E3: bit planes of both planes into this tile's heap slot; then lane j
+    // of the wave writes width, anchor and offset of the wave's stream block j
+    for (int jb = wave; jb < NAB; jb += NW) {
+        const int l = jb * 64 + lane;
+        const uint32_t ur = reinterpret_cast<const uint32_t *>(sre)[l * VPT];
+        const uint32_t ui = reinterpret_cast<const uint32_t *>(sim)[l * VPT];
+        const uint32_t Wr = sW[2 * jb], Wi = sW[2 * jb + 1];
+        const uint64_t mr = pack_planes(ur, Wr);
+        const uint64_t mi = pack_planes(ui, Wi);
+        if ((uint32_t)lane < Wr) out.heap[slot + sOff[2 * jb] + lane] = mr;
+        if ((uint32_t)lane < Wi) out.heap[slot + sOff[2 * jb + 1] + lane] = mi;
     }
-    for (int j0 = 0; j0 < BPW; j0 += 64) {
-        const int j = j0 + lane;
-        if (j < BPW && wave + NW * j < NSB) {
-            const int bt = wave + NW * j;
-            const int jb = bt >> 1, p = bt & 1;
-            const uint64_t bi = block_index(out, 2 * sG[jb] + (uint64_t)p);
+    constexpr int APW = (NAB + NW - 1) / NW;
+    for (int j0 = 0; j0 < 2 * APW; j0 += 64) {
+        const int j = j0 + lane;                 // stream block j of the wave: amplitude block j / 2
+        const int jb = wave + NW * (j >> 1);
+        if (j < 2 * APW && jb < NAB) {
+            const int bt = 2 * jb + (j & 1);
+            const uint64_t bi = block_index(out, 2 * sG[jb] + (uint64_t)(j & 1));
             out.W[bi] = (uint8_t)sW[bt];
             out.A[bi] = sA[bt];
             out.OFF[bi] = (uint32_t)(slot + sOff[bt]);
@@ -228,7 +243,7 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
 // into registers and writes RPT output rows; when there are fewer groups than
 // threads, adjacent lanes of one wave share a group (all loads of a wave are
 // issued before its stores, so sharing is race-free).
-template <typename T, int TB, int K>
+template <typename T, int TB, int K, bool REAL>
 __device__ __forceinline__ void op_dense(T *__restrict__ sre, T *__restrict__ sim, const OpDesc &op,
                                          const T *__restrict__ M)
 {
@@ -268,13 +283,22 @@ __device__ __forceinline__ void op_dense(T *__restrict__ sre, T *__restrict__ si
         for (int rr = 0; rr < RPT; ++rr) {
             const int r = rb * RPT + rr;
             T ar = 0, ai = 0;
+            if (REAL) {
 #pragma unroll
-            for (int s = 0; s < D; ++s) {
-                const T mr = M[2 * (r * D + s)], mi = M[2 * (r * D + s) + 1];
-                ar = fmaT(mr, vr[s], ar);
-                ar = fmaT(-mi, vi[s], ar);
-                ai = fmaT(mr, vi[s], ai);
-                ai = fmaT(mi, vr[s], ai);
+                for (int s = 0; s < D; ++s) {
+                    const T mr = M[2 * (r * D + s)];
+                    ar = fmaT(mr, vr[s], ar);
+                    ai = fmaT(mr, vi[s], ai);
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < D; ++s) {
+                    const T mr = M[2 * (r * D + s)], mi = M[2 * (r * D + s) + 1];
+                    ar = fmaT(mr, vr[s], ar);
+                    ar = fmaT(-mi, vi[s], ar);
+                    ai = fmaT(mr, vi[s], ai);
+                    ai = fmaT(mi, vr[s], ai);
+                }
             }
             int lr = l0;
 #pragma unroll
@@ -414,12 +438,22 @@ __device__ __forceinline__ void apply_op(T *sre, T *sim, const OpDesc &op, const
 {
     if (op.type == OP_DENSE || op.type == OP_MFMA) {
         if (op.ctrl_fixed == 0 || (base & op.ctrl_fixed) == op.ctrl_fixed) {
-            switch (op.k) {
-            case 1: op_dense<T, TB, 1>(sre, sim, op, M); break;
-            case 2: op_dense<T, TB, 2>(sre, sim, op, M); break;
-            case 3: op_dense<T, TB, (KMAX >= 3 ? 3 : 1)>(sre, sim, op, M); break;
-            case 4: op_dense<T, TB, (KMAX >= 4 ? 4 : 1)>(sre, sim, op, M); break;
-            default: op_dense<T, TB, (KMAX >= 5 ? 5 : 1)>(sre, sim, op, M); break;
+            if (op.real) {
+                switch (op.k) {
+                case 1: op_dense<T, TB, 1, true>(sre, sim, op, M); break;
+                case 2: op_dense<T, TB, 2, true>(sre, sim, op, M); break;
+                case 3: op_dense<T, TB, (KMAX >= 3 ? 3 : 1), true>(sre, sim, op, M); break;
+                case 4: op_dense<T, TB, (KMAX >= 4 ? 4 : 1), true>(sre, sim, op, M); break;
+                default: op_dense<T, TB, (KMAX >= 5 ? 5 : 1), true>(sre, sim, op, M); break;
+                }
+            } else {
+                switch (op.k) {
+                case 1: op_dense<T, TB, 1, false>(sre, sim, op, M); break;
+                case 2: op_dense<T, TB, 2, false>(sre, sim, op, M); break;
+                case 3: op_dense<T, TB, (KMAX >= 3 ? 3 : 1), false>(sre, sim, op, M); break;
+                case 4: op_dense<T, TB, (KMAX >= 4 ? 4 : 1), false>(sre, sim, op, M); break;
+                default: op_dense<T, TB, (KMAX >= 5 ? 5 : 1), false>(sre, sim, op, M); break;
+                }
             }
         }
     } else if (op.type == OP_DIAG) {

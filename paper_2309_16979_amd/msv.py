@@ -232,6 +232,40 @@ def codec_decode(blob: bytes, dtype: str = "c64") -> np.ndarray:
     return out
 
 
+def plan(n: int, gates: Sequence, log2_tile: int = 12, k_max: int = 2, lookahead: int = 64):
+    """The passes and fused ops msv_apply would run (host-side planning only).
+
+    Returns (n_passes, ops) where each op is a dict with keys pass, type
+    ("dense", "diag", "phase"), qubits, ctrl_mask, tile_mask, hub and data
+    (matrix, diagonal, or (G, mu, lam) for a controlled phase)."""
+    Lb = load()
+    arr, keep = gate_array(gates)
+    used = C.c_size_t(0)
+    npass = C.c_uint64(0)
+    check(Lb.msv_plan_export(n, arr, len(gates), log2_tile, k_max, lookahead, None, 0, C.byref(used),
+                             C.byref(npass)))
+    buf = np.zeros(max(1, used.value))
+    check(Lb.msv_plan_export(n, arr, len(gates), log2_tile, k_max, lookahead, buf.ctypes.data, buf.size,
+                             C.byref(used), C.byref(npass)))
+    ops, i = [], 0
+    names = {0: "dense", 1: "diag", 3: "phase"}
+    while i < used.value:
+        p_, t, k = int(buf[i]), int(buf[i + 1]), int(buf[i + 2])
+        q = [int(v) for v in buf[i + 3:i + 3 + k]]
+        ctrl, tile, hub, ln = int(buf[i + 8]), int(buf[i + 9]), int(buf[i + 10]), int(buf[i + 11])
+        d = buf[i + 12:i + 12 + ln]
+        if t == 3:
+            data = (complex(d[0], d[1]), d[2:2 + n].copy(), d[2 + n:2 + 2 * n].copy())
+        else:
+            c = d[0::2] + 1j * d[1::2]
+            data = c.reshape(1 << k, 1 << k) if t == 0 else c
+        ops.append({"pass": p_, "type": names[t], "qubits": q, "ctrl_mask": ctrl, "tile_mask": tile,
+                    "hub": hub, "data": data})
+        i += 12 + ln
+    del keep
+    return int(npass.value), ops
+
+
 def batch_run(circuits, dtype: str = "c64", eb: float = 1e-4, autotune: bool = True, k_max: int = 2,
               log2_tile: int = 0, mma: str = "f32", want_amplitudes: bool = False):
     """Run many circuits, each given as (n, gates, init_basis), with one launch
