@@ -98,6 +98,8 @@ typedef struct msv_stats {
                                     last apply: per pass, compressed blocks read and
                                     written (payload + 9 bytes of W/A/OFF per block)
                                     or 2 x 2^n x sizeof(complex) uncompressed      */
+    uint64_t mfma_ops;           /* fused ops of the last apply run on the matrix
+                                    cores (k >= option "mfma_min_k")              */
 } msv_stats;
 
 typedef struct msv_sim msv_sim;  /* opaque, library-owned */
@@ -126,18 +128,32 @@ int msv_set_error_bound(msv_sim *sim, double eb);
 /* MSV_STORE_DEVICE (compressed chunks in HBM) or MSV_STORE_HOST_PINNED
  * (compressed chunks in pinned host memory, streamed per pass). */
 int msv_set_store(msv_sim *sim, int store);
-/* Fuse consecutive gates into dense unitaries of at most k_max (1..5) qubits;
- * mma_precision selects the arithmetic of fused ops (enum msv_mma). */
+/* Fuse consecutive gates into dense unitaries of at most k_max (1..5) qubits
+ * (Sec. 2: a gate group is applied in one pass). Fused ops of k >= 3 qubits
+ * (and k >= option "mfma_min_k") run on the matrix cores as the real GEMM
+ * [[Ur, -Ui], [Ui, Ur]] x [Xr; Xi] when the tile holds at least 16 groups of
+ * 2^k amplitudes; mma_precision picks their arithmetic:
+ *   MSV_MMA_F64  complex128 states, FP64 MFMA;
+ *   MSV_MMA_F32  complex64 states, FP32 MFMA (default for complex64);
+ *   MSV_MMA_BF16 complex64 states, inputs rounded to BF16 (nearest even),
+ *                FP32 accumulation: each output within 2^-7 (1 + 2^-6) of
+ *                sum_c |R_ic X_c| of the exact product.
+ * Narrower ops run on the VALU in the state's precision. MSV_E_ARG for a
+ * precision that does not match the dtype. */
 int msv_set_fusion(msv_sim *sim, int k_max, int mma_precision);
 /* Named numeric options:
  *   "tile_qubits"  log2 amplitudes per workgroup tile (6..13; 0 = automatic)
  *   "renormalize"  1 = rescale to unit norm at the next decode after each pass
  *   "check_bound"  1 (default) = FP64 max |x - x'| per pass
- *   "mfma_min_k"   smallest fused width run on matrix cores (3..6; 6 = never)
+ *   "mfma_min_k"   smallest fused width run on matrix cores (3..6, default 3;
+ *                  6 = never)
  *   "batch_chunks" host store: chunks per streamed batch (0 = automatic)
  *   "time_passes"  1 = time every pass kernel with events (msv_stats.t_pass)
  *   "lookahead"    gates the planner scans past a deferred gate to pull
  *                  commuting gates into the current pass (default 64, 0 = none)
+ *   "segments"     1 (default) = run runs of 1-2 qubit dense ops, diagonals and
+ *                  controlled phases on per-thread registers (tiles of 2^10 ..
+ *                  2^13), one LDS round trip per run; 0 = one per op
  *   "autotune"     1 = choose fusion width and tile size per msv_apply from a
  *                  cost model calibrated once per process on the GPU */
 int msv_set_option(msv_sim *sim, const char *key, double value);

@@ -122,6 +122,8 @@ double bound_for(const msv_sim *s, double norm2)
     return s->eb * (1.0 + std::ldexp(1.0, -20)) + 2.0 * uT * std::max(xmax, s->eb);
 }
 
+int mma_mode(const msv_sim *s) { return s->mma == MSV_MMA_BF16 ? MMA_BF16 : MMA_NATIVE; }
+
 // Size of the state in the canonical chunk format: headers, W and A arrays of
 // every chunk (GENERAL chunks assumed) and the payload words.
 uint64_t canonical_bytes(const msv_sim *s, uint64_t words)
@@ -169,6 +171,8 @@ int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOpt
         ok = lower_passes<float>(passes, o, ops, poolf, geoms);
         pool_bytes = poolf.size() * sizeof(float);
     }
+    s->stats.mfma_ops = 0;
+    for (const OpDesc &d : ops) s->stats.mfma_ops += d.type == OP_MFMA;
     if (!ok) return fail(s, MSV_E_ARG, "internal planner error: op outside its tile");
     const size_t n_passes = geoms.size();
     std::vector<uint64_t> offs(n_passes + 1, 0);
@@ -412,6 +416,8 @@ int msv_set_option(msv_sim *s, const char *key, double v)
     } else if (!strcmp(key, "lookahead")) {
         if (v != iv || iv < 0 || iv > 4096) return fail(s, MSV_E_ARG, "lookahead in 0..4096");
         s->lookahead = iv;
+    } else if (!strcmp(key, "segments")) {
+        s->segments = v != 0.0;
     } else if (!strcmp(key, "autotune")) {
         s->autotune = v != 0.0;
     } else if (!strcmp(key, "time_passes")) {
@@ -583,6 +589,8 @@ int msv_apply(msv_sim *s, const msv_gate *gates, size_t n_gates)
         o.tb = choose_tile_bits(s);
         o.k_max = s->k_max;
         o.mfma_min_k = s->mfma_min_k;
+        o.mma = mma_mode(s);
+        o.segments = s->segments;
         o.lookahead = s->lookahead;
         std::vector<Pass> passes;
         if (s->autotune && s->compressed()) {

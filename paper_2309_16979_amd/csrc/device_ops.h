@@ -17,6 +17,17 @@ enum OpType : int32_t {
     OP_PHASE = 3,   // controlled linear phase: factor(g) = A(g) * (b_c(g) ? B(g) : 1)
     OP_GRAD = 4,    // adjoint probe: per-tile partial <lambda| A |psi> into a gradient slot
     OP_OBS = 5,     // multiply by the diagonal observable sum_k c_k Z(m_k)
+    OP_RPHASE = 6,  // controlled linear phase inside a register segment (own table layout)
+    OP_SEG = 7,     // start of a register segment: the next k ops run on per-thread
+                    // registers; pos[0..TB-8) = register tile bits (ascending),
+                    // ctrl_local = their mask
+};
+
+// Matrix-core mode of a pass launch.
+enum MmaMode : int32_t {
+    MMA_NONE = 0,     // every dense op on the VALU
+    MMA_NATIVE = 1,   // inputs in the state's type: FP32 16x16x4 or FP64 16x16x4 MFMA
+    MMA_BF16 = 2,     // BF16 inputs, FP32 accumulation: 16x16x16 MFMA (complex64 states)
 };
 
 // One kernel-level operation of a pass. Matrices live in a per-apply pool.
@@ -50,8 +61,8 @@ struct PassGeom {
     uint64_t nontile_mask; // global bits that index tiles
     uint64_t tile_begin;   // first tile of this launch
     uint64_t n_tiles;      // tiles in this launch
-    int32_t max_k;         // widest dense op of the pass (selects the kernel variant)
-    int32_t pad_;
+    int32_t max_k;         // widest VALU dense op of the pass (selects the kernel variant)
+    int32_t mma;           // matrix-core mode of the pass's OP_MFMA ops (MmaMode), 0 = none
 };
 
 }  // namespace msv

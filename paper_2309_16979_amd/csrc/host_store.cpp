@@ -386,6 +386,8 @@ int apply_host_store(msv_sim *s, const std::vector<Prim> &prims, size_t n_gates)
     o.tb = choose_tile_bits(s);
     o.k_max = s->k_max;
     o.mfma_min_k = s->mfma_min_k;
+    o.mma = mma_mode(s);
+    o.segments = s->segments;
     o.lookahead = s->lookahead;
     std::vector<Pass> passes = plan_passes(prims, o);
     std::vector<OpDesc> ops;
@@ -395,6 +397,8 @@ int apply_host_store(msv_sim *s, const std::vector<Prim> &prims, size_t n_gates)
     const bool ok = s->is_double() ? lower_passes<double>(passes, o, ops, pd, geoms)
                                    : lower_passes<float>(passes, o, ops, pf, geoms);
     if (!ok) return fail_sim(s, MSV_E_ARG, "internal planner error");
+    s->stats.mfma_ops = 0;
+    for (const OpDesc &d : ops) s->stats.mfma_ops += d.type == OP_MFMA;
     int st;
     const size_t ops_bytes = ops.size() * sizeof(OpDesc);
     const size_t pool_bytes = s->is_double() ? pd.size() * 8 : pf.size() * 4;

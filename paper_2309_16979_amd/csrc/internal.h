@@ -14,6 +14,8 @@ void host_free(HostMem &m);
 int ensure_stream(msv_sim *s);
 int choose_tile_bits(const msv_sim *s);
 double bound_for(const msv_sim *s, double norm2);
+// Matrix-core mode (MmaMode) for the state's dtype and its MSV_MMA_* setting.
+int mma_mode(const msv_sim *s);
 
 int alloc_device_store(msv_sim *s);
 int pin_stage(msv_sim *s, size_t bytes);

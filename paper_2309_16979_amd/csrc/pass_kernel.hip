@@ -1,129 +1,28 @@
-// The fused streamed pass: load (decode) -> apply every op of the pass in LDS
-// -> store (encode), one workgroup per tile of 2^TB amplitudes.
-//
-// A pass (one stage of the paper's online loop, Sec. 2) is a run of gates whose
-// non-diagonal qubits all fit into one tile: the tile's first six bits are
-// qubits 0..5 (so it consists of whole 64-amplitude codec blocks) and its other
-// TB-6 bits are the pass's qubits, which may lie inside a chunk or cross chunks
-// (then the workgroup gathers blocks from 2^h chunks: the chunk-pair exchange).
-// Every workgroup decodes its blocks into LDS (planar re / im), runs the op
-// list with a barrier between ops, and re-encodes its blocks. Encoded payload
-// goes to the workgroup's own heap slot (worst case 32 words per block), so
-// no cross-workgroup scan is needed; W / A / OFF record where each block went.
+// Launch of the fused streamed pass kernel (pass_kernel.h): picks the variant
+// for the state's type and the pass's matrix-core mode.
 #include <hip/hip_runtime.h>
 
-#include "tile_ops.h"
+#include "pass_kernel.h"
 
 namespace msv {
 
-template <typename T, int TB, bool LOADC, bool STOREC, int KMAX>
-__global__ __launch_bounds__(kThreads) void pass_kernel(PassGeom geo, PassBuffers buf)
-{
-    constexpr int TILE = 1 << TB;
-    constexpr int NAB = TILE >> 6;   // 64-amplitude blocks per tile
-    constexpr int NSB = 2 * NAB;     // stream blocks (re + im planes)
-    constexpr int NW = kThreads / 64;
-
-    __shared__ T sre[TILE];
-    __shared__ T sim[TILE];
-    __shared__ uint64_t sG[NAB];
-    __shared__ uint32_t sW[NSB];
-    __shared__ int32_t sA[NSB];
-    __shared__ uint32_t sOff[NSB];
-    __shared__ double sred[2 * NW];
-    __shared__ T sph[PhaseScratch<TB>::size];
-
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform for the compiler
-    const uint64_t tile = geo.tile_begin + blockIdx.x;
-    const uint64_t base = tile_base(geo, tile);
-    tile_blocks<TB>(geo, base, sG);
-    __syncthreads();
-
-    const double sc = buf.scale_src ? 1.0 / __builtin_sqrt(*buf.scale_src) : buf.scale;
-    tile_load<T, TB, LOADC>(sre, sim, sG, buf.amps_in, buf.in, buf.step, sc, wave, lane);
-    __syncthreads();
-
-    const T *pool = (const T *)buf.pool;
-    for (int oi = 0; oi < geo.n_ops; ++oi) {
-        const OpDesc op = buf.ops[geo.op_begin + oi];
-        if (op.type == OP_OBS)
-            op_obs<T, TB>(sre, sim, sG, buf.obs_masks, buf.obs_coeffs, buf.obs_terms);
-        else
-            apply_op<T, TB, KMAX>(sre, sim, op, pool + 2 * (int64_t)op.mat, base, geo.n, sph);
-        __syncthreads();
-    }
-
-    double nrm = 0.0, err = 0.0;
-    const uint64_t slot = (tile - buf.slot_tile0) * (uint64_t)(32 * NSB);
-    const uint32_t words = tile_store<T, TB, STOREC>(sre, sim, sG, sW, sA, sOff, buf.amps_out, buf.out, slot,
-                                                     buf.inv_step, buf.step, buf.check_err, buf.flags, nrm, err,
-                                                     wave, lane);
-    // per-workgroup statistics (fixed reduction order)
-    nrm = wave_sum_f64(nrm);
-    err = wave_max_f64(err);
-    if (lane == 0) { sred[wave] = nrm; sred[NW + wave] = err; }
-    __syncthreads();
-    if (tid == 0 && buf.part) {
-        double a = 0.0, e = 0.0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) { a += sred[w]; e = fmax(e, sred[NW + w]); }
-        buf.part[3 * blockIdx.x] = a;
-        buf.part[3 * blockIdx.x + 1] = e;
-        buf.part[3 * blockIdx.x + 2] = (double)words;
-    }
-}
-
-template <typename T, int TB, int KMAX>
-static hipError_t launch_k(bool load_c, bool store_c, const PassGeom &geo, const PassBuffers &buf,
-                           hipStream_t stream)
-{
-    const dim3 grid((unsigned)geo.n_tiles), block(kThreads);
-    if (load_c && store_c)
-        hipLaunchKernelGGL((pass_kernel<T, TB, true, true, KMAX>), grid, block, 0, stream, geo, buf);
-    else if (load_c)
-        hipLaunchKernelGGL((pass_kernel<T, TB, true, false, KMAX>), grid, block, 0, stream, geo, buf);
-    else if (store_c)
-        hipLaunchKernelGGL((pass_kernel<T, TB, false, true, KMAX>), grid, block, 0, stream, geo, buf);
-    else
-        hipLaunchKernelGGL((pass_kernel<T, TB, false, false, KMAX>), grid, block, 0, stream, geo, buf);
-    return hipGetLastError();
-}
-
-// Passes whose dense ops are at most 3 qubits wide run a variant compiled
-// without the 4- and 5-qubit paths (fewer registers, higher occupancy).
-template <typename T, int TB>
-static hipError_t launch_tb(bool load_c, bool store_c, const PassGeom &geo, const PassBuffers &buf,
-                            hipStream_t stream)
-{
-    if (geo.max_k <= 3) return launch_k<T, TB, 3>(load_c, store_c, geo, buf, stream);
-    return launch_k<T, TB, 5>(load_c, store_c, geo, buf, stream);
-}
-
-template <typename T>
-static hipError_t launch_t(bool load_c, bool store_c, const PassGeom &geo, const PassBuffers &buf,
-                           hipStream_t stream)
-{
-    switch (geo.tb) {
-    case 6: return launch_tb<T, 6>(load_c, store_c, geo, buf, stream);
-    case 7: return launch_tb<T, 7>(load_c, store_c, geo, buf, stream);
-    case 8: return launch_tb<T, 8>(load_c, store_c, geo, buf, stream);
-    case 9: return launch_tb<T, 9>(load_c, store_c, geo, buf, stream);
-    case 10: return launch_tb<T, 10>(load_c, store_c, geo, buf, stream);
-    case 11: return launch_tb<T, 11>(load_c, store_c, geo, buf, stream);
-    case 12: return launch_tb<T, 12>(load_c, store_c, geo, buf, stream);
-    case 13: return launch_tb<T, 13>(load_c, store_c, geo, buf, stream);
-    default: return hipErrorInvalidValue;
-    }
-}
+template <typename T, int MF>
+hipError_t launch_pass_variant(bool, bool, const PassGeom &, const PassBuffers &, hipStream_t);
 
 hipError_t launch_pass(bool is_double, bool load_c, bool store_c, const PassGeom &geo, const PassBuffers &buf,
                        hipStream_t stream)
 {
     if (geo.n_tiles == 0) return hipSuccess;
     if (geo.n_tiles > 0x7fffffffull) return hipErrorInvalidValue;
-    return is_double ? launch_t<double>(load_c, store_c, geo, buf, stream)
-                     : launch_t<float>(load_c, store_c, geo, buf, stream);
+    if (is_double) {
+        if (geo.mma == MMA_NONE) return launch_pass_variant<double, MMA_NONE>(load_c, store_c, geo, buf, stream);
+        if (geo.mma == MMA_NATIVE) return launch_pass_variant<double, MMA_NATIVE>(load_c, store_c, geo, buf, stream);
+        return hipErrorInvalidValue;
+    }
+    if (geo.mma == MMA_NONE) return launch_pass_variant<float, MMA_NONE>(load_c, store_c, geo, buf, stream);
+    if (geo.mma == MMA_NATIVE) return launch_pass_variant<float, MMA_NATIVE>(load_c, store_c, geo, buf, stream);
+    if (geo.mma == MMA_BF16) return launch_pass_variant<float, MMA_BF16>(load_c, store_c, geo, buf, stream);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace msv

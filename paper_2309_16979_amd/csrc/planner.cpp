@@ -457,7 +457,68 @@ bool lower_passes(const std::vector<Pass> &passes, const PlanOptions &o, std::ve
                 if (ps.tile_q[i] == q) return i;
             return -1;
         };
-        for (const HostOp &h : ps.ops) {
+        // Register segments: maximal runs of ops that can act on per-thread
+        // registers (dense ops of <= 2 qubits whose tile bits fit in R register
+        // bits together with the run's other dense ops, diagonals, controlled
+        // phases). Each run costs one LDS round trip instead of one per op.
+        const int RB = tb - 8;   // register bits per thread
+        const bool use_seg = o.segments && RB >= 2 && RB <= 5;
+        std::vector<int> seg_id(ps.ops.size(), -1);
+        std::vector<uint32_t> seg_mask;
+        if (use_seg) {
+            int cur = -1;
+            for (size_t i = 0; i < ps.ops.size(); ++i) {
+                const HostOp &h = ps.ops[i];
+                uint32_t P = 0;
+                bool joinable = false;
+                if (h.type == OP_DENSE && h.q.size() <= 2 && !h.q.empty()) {
+                    joinable = true;
+                    for (int q : h.q) {
+                        const int p = tpos(q);
+                        if (p < 0) joinable = false;
+                        else P |= 1u << p;
+                    }
+                } else if (h.type == OP_DIAG || h.type == OP_PHASE) {
+                    joinable = true;
+                }
+                if (!joinable) {
+                    cur = -1;
+                    continue;
+                }
+                if (cur >= 0 && __builtin_popcount(seg_mask[cur] | P) <= RB) {
+                    seg_mask[cur] |= P;
+                } else {
+                    cur = (int)seg_mask.size();
+                    seg_mask.push_back(P);
+                }
+                seg_id[i] = cur;
+            }
+            // complete each register set with the highest free tile bits, so
+            // that the low tile bits (consecutive LDS words) stay thread bits
+            for (uint32_t &m : seg_mask)
+                for (int p = tb - 1; p >= 0 && __builtin_popcount(m) < RB; --p) m |= 1u << p;
+        }
+        int open_seg = -1;
+        for (size_t hi = 0; hi < ps.ops.size(); ++hi) {
+            const HostOp &h = ps.ops[hi];
+            const int sid = seg_id[hi];
+            if (sid >= 0 && sid != open_seg) {
+                open_seg = sid;
+                OpDesc sd{};
+                sd.type = OP_SEG;
+                int cnt = 0;
+                for (size_t j = hi; j < ps.ops.size() && seg_id[j] == sid; ++j) ++cnt;
+                sd.k = cnt;
+                for (int m = 0; m < 5; ++m) { sd.pos[m] = -1; sd.gq[m] = -1; }
+                int r = 0;
+                for (int p = 0; p < tb; ++p)
+                    if ((seg_mask[sid] >> p) & 1u) sd.pos[r++] = p;
+                sd.ctrl_local = seg_mask[sid];
+                sd.ctrl_pos = -1;
+                sd.ctrl_q = -1;
+                sd.slot = -1;
+                ops.push_back(sd);
+            }
             OpDesc d{};
             d.type = h.type;
             d.mat = (int32_t)(pool.size() / 2);
@@ -469,7 +530,8 @@ bool lower_passes(const std::vector<Pass> &passes, const PlanOptions &o, std::ve
             for (int m = 0; m < 5; ++m) { d.pos[m] = -1; d.gq[m] = -1; }
             if (h.type == OP_DENSE) {
                 d.k = (int32_t)h.q.size();
-                if (d.k >= o.mfma_min_k) d.type = OP_MFMA;
+                // matrix cores need k >= 3 and 16 columns of 2^k amplitudes per tile
+                if (o.mma != 0 && d.k >= 3 && d.k >= o.mfma_min_k && tb - d.k >= 4) d.type = OP_MFMA;
                 ok = ok && d.k >= 1 && d.k <= kMaxFuse && (int)h.m.size() == (1 << (2 * d.k));
                 for (int m = 0; m < d.k; ++m) {
                     d.pos[m] = tpos(h.q[m]);
@@ -480,7 +542,17 @@ bool lower_passes(const std::vector<Pass> &passes, const PlanOptions &o, std::ve
                 for (const cd &v : h.m)
                     if (v.imag() != 0.0) d.real = 0;
                 d.ctrl_fixed = h.ctrl_mask;
-                for (const cd &v : h.m) push(v);
+                if (d.k == 2 && d.type == OP_DENSE && d.pos[0] > d.pos[1]) {
+                    // two-qubit ops take their tile bits ascending (register
+                    // segments need it; the LDS path uses the same matrix so
+                    // that both sum in the same order): swap the index bits
+                    std::swap(d.pos[0], d.pos[1]);
+                    auto sw = [](int v) { return ((v & 1) << 1) | ((v >> 1) & 1); };
+                    for (int r = 0; r < 4; ++r)
+                        for (int c = 0; c < 4; ++c) push(h.m[sw(r) * 4 + sw(c)]);
+                } else {
+                    for (const cd &v : h.m) push(v);
+                }
             } else if (h.type == OP_GRAD) {
                 d.k = (int32_t)h.q.size();
                 d.slot = h.slot;
@@ -503,6 +575,45 @@ bool lower_passes(const std::vector<Pass> &passes, const PlanOptions &o, std::ve
                     d.pos[m] = tpos(h.q[m]);
                 }
                 for (const cd &v : h.m) push(v);
+            } else if (sid >= 0) {
+                // controlled phase on registers: factor = F(thread, tile id) U(register index)
+                d.type = OP_RPHASE;
+                d.ctrl_q = h.hub;
+                d.ctrl_pos = h.hub >= 0 ? tpos(h.hub) : -1;
+                const int G = (n - tb + 7) / 8;
+                d.k = G;
+                const uint32_t S = seg_mask[sid];
+                std::vector<int> sp, tp, nq;
+                for (int p = 0; p < tb; ++p) ((S >> p) & 1u ? sp : tp).push_back(ps.tile_q[p]);
+                for (int q = 0; q < n; ++q)
+                    if ((g.nontile_mask >> q) & 1ull) nq.push_back(q);
+                // per-qubit factors, then every table as subset products
+                // (entry v = entry of v without its lowest bit times that bit's factor)
+                std::vector<cd> fa(n), fab(n);
+                for (int q = 0; q < n; ++q) {
+                    fa[q] = expi(h.mu[q]);
+                    fab[q] = expi(h.mu[q] + h.lam[q]);
+                }
+                auto subset_table = [&](const std::vector<int> &qs, int size, const std::vector<cd> &f, cd first) {
+                    std::vector<cd> t(size);
+                    t[0] = first;
+                    for (int v = 1; v < size; ++v) {
+                        const int b = __builtin_ctz(v);
+                        t[v] = b < (int)qs.size() ? t[v & (v - 1)] * f[qs[b]] : t[v & (v - 1)];
+                    }
+                    return t;
+                };
+                for (int on = 0; on < 2; ++on)
+                    for (const cd &v : subset_table(sp, 1 << RB, on ? fab : fa, h.global)) push(v);
+                for (int on = 0; on < 2; ++on)
+                    for (const cd &v : subset_table(tp, 256, on ? fab : fa, 1.0)) push(v);
+                for (int on = 0; on < 2; ++on)
+                    for (int gg = 0; gg < G; ++gg) {
+                        std::vector<int> qs;
+                        for (int j = 0; j < 8 && 8 * gg + j < (int)nq.size(); ++j) qs.push_back(nq[8 * gg + j]);
+                        for (const cd &v : subset_table(qs, 256, on ? fab : fa, 1.0)) push(v);
+                    }
+                ok = ok && (int)sp.size() == RB && (int)tp.size() == 8;
             } else {
                 d.k = 0;
                 d.ctrl_q = h.hub;
@@ -539,9 +650,13 @@ bool lower_passes(const std::vector<Pass> &passes, const PlanOptions &o, std::ve
             ops.push_back(d);
         }
         ok = ok && (int)ps.tile_q.size() == tb && ps.tile_q[0] == 0 && ps.tile_q[5] == 5;
+        g.n_ops = (int32_t)(ops.size() - (size_t)g.op_begin);   // segment markers included
         g.max_k = 0;
-        for (int i = g.op_begin; i < (int)ops.size(); ++i)
-            if (ops[i].type == OP_DENSE || ops[i].type == OP_MFMA) g.max_k = std::max<int>(g.max_k, ops[i].k);
+        g.mma = 0;
+        for (int i = g.op_begin; i < (int)ops.size(); ++i) {
+            if (ops[i].type == OP_DENSE) g.max_k = std::max<int>(g.max_k, ops[i].k);
+            if (ops[i].type == OP_MFMA) g.mma = o.mma;
+        }
         geoms.push_back(g);
     }
     return ok;

@@ -75,11 +75,12 @@ struct Workspace {
 struct msv_sim {
     int n = 0, dtype = MSV_C64, log2c = 20, store = MSV_STORE_DEVICE;
     double eb = 0.0;
-    int k_max = 2, mma = MSV_MMA_F32, tile_bits = 0, renorm = 0, check_bound = 1, mfma_min_k = 6;
+    int k_max = 2, mma = MSV_MMA_F32, tile_bits = 0, renorm = 0, check_bound = 1, mfma_min_k = 3;
     int batch_chunks = 0;
     int time_passes = 0;
     int autotune = 0;
     int lookahead = 64;
+    int segments = 1;                // register segments in pass kernels
     int tuned_k = 0, tuned_tb = 0;   // last autotuner choice
     void *(*alloc)(size_t, void *) = nullptr;
     void (*dealloc)(void *, void *) = nullptr;
