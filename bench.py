@@ -11,6 +11,18 @@ including the codec = steps * gates * 2^n / time.
 Prints one JSON line with the driver's fields plus "roofline" (pass kernel,
 durations from HIP events around every pass launch on the stream it runs on)
 and "cpu_baseline" (the FP64 oracle on a bounded sample of the same circuit).
+
+The compressed pass is bound by vector-ALU work (codec bit planes, prefix
+sums, FP64 quantisation, gate arithmetic), not by HBM: its roofline is the
+chip's vector lane-operation rate, 256 CUs x 64 lanes x 2.4 GHz, against the
+algorithmic lane operations the library counts for each pass (gate
+arithmetic per amplitude, W + 15 per codec value and direction). The HBM view
+(algorithmic bytes / time, and counter-measured traffic) is reported beside it.
+
+Other workloads (--workload): host34 (n=34 state as compressed chunks in
+pinned host memory), adjoint22 (adjoint gradient of a 6-layer ansatz at
+n=22), batch256 (256 circuits of 12..24 qubits, plus 64 batched adjoint
+parameter sets at n=18). Each prints its own JSON line.
 """
 
 from __future__ import annotations
@@ -28,6 +40,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_GOPS = 256 * 64 * 2.4   # lane operations per ns = Gop/s
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "f64": 78.6}
 
 
 def parse():
@@ -44,6 +58,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip comparison runs outside the timed loop")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--workload", default="qft28", choices=["qft28", "host34", "adjoint22", "batch256"])
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 256 MiB device copy (scales the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -110,6 +127,16 @@ def main():
         from paper_2309_16979_amd import build
         build.build()
     torch.cuda.set_device(0)
+    if a.copy_probe:
+        src = torch.ones(1 << 26, device="cuda")   # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": src.numel() * 4}))
+        return
+    if a.workload != "qft28":
+        {"host34": bench_host34, "adjoint22": bench_adjoint22, "batch256": bench_batch256}[a.workload](a)
+        return
     n = a.n
     x, gates = qft_plus_random(n, 100, seed=a.seed)
     masks, coeffs = zz_chain(n)
@@ -130,6 +157,8 @@ def main():
     t_pass = 0.0
     n_pass = 0
     pass_bytes = 0
+    valu_ops = 0.0
+    mfma_flops = 0.0
     t0 = time.perf_counter()
     for _ in range(a.steps):
         zz = run(sim)
@@ -137,6 +166,8 @@ def main():
         t_pass += st["t_pass"]
         n_pass += st["passes"]
         pass_bytes += st["pass_bytes"]
+        valu_ops += st["pass_valu_ops"]
+        mfma_flops += st["pass_mfma_flops"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = a.steps * G * float(1 << n) / dt
@@ -144,13 +175,23 @@ def main():
 
     avg_pass = t_pass / max(1, n_pass)
     bytes_per_pass = pass_bytes / max(1, n_pass)
-    achieved = bytes_per_pass / avg_pass / 1e9 if avg_pass > 0 else 0.0
-    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_from_profiles("bytes_per_launch"),
-            "kernel": "pass_kernel<float,%d,true,true>" % (a.tile or 12),
+    valu_per_pass = valu_ops / max(1, n_pass)
+    achieved_gbs = bytes_per_pass / avg_pass / 1e9 if avg_pass > 0 else 0.0
+    achieved_gops = valu_per_pass / avg_pass / 1e9 if avg_pass > 0 else 0.0
+    traffic = traffic_from_profiles("bytes_per_launch")
+    roof = {"bound": "alu", "achieved": round(achieved_gops, 1), "peak": round(VALU_PEAK_GOPS, 1),
+            "unit": "Gop/s (vector lane operations)", "frac": round(achieved_gops / VALU_PEAK_GOPS, 4),
+            "traffic": traffic,
+            "kernel": "pass_kernel<float,%d,true,true,*,%d>" % (a.tile or 12, 0 if a.k < 3 else 1),
             "avg_launch_ms": round(avg_pass * 1e3, 4), "launches": n_pass,
-            "algorithmic_bytes_per_launch": int(bytes_per_pass)}
+            "algorithmic_ops_per_launch": valu_per_pass,
+            "hbm": {"achieved": round(achieved_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+                    "algorithmic_bytes_per_launch": int(bytes_per_pass),
+                    "traffic_achieved": round(traffic / avg_pass / 1e9, 2) if traffic and avg_pass else None}}
+    if mfma_flops > 0 and avg_pass > 0:
+        roof["mfma"] = {"achieved": round(mfma_flops / max(1, n_pass) / avg_pass / 1e12, 3),
+                        "peak": MFMA_PEAK_TFLOPS[a.mma], "unit": "TFLOP/s"}
 
     out = {"metric": "amplitude-gate updates/sec incl. codec", "value": value,
            "unit": "amplitude-gate updates/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -180,7 +221,6 @@ def main():
         run(sim)
         fr, fn = sim.fidelity(amps_ref)
         sim.close()
-        del amps_ref
         plain = Simulator(n, dtype="c64", eb=0.0, k_max=a.k, mma=a.mma, options={"time_passes": 1})
         run(plain)
         t1 = time.perf_counter()
@@ -190,6 +230,22 @@ def main():
         pst = plain.stats()
         plain.close()
         out["fidelity_vs_fp64"] = {"f_raw": fr, "f_norm": fn, "reference": "complex128 uncompressed GPU run"}
+        # fused width k on the matrix cores (FP32 / BF16 inputs), same workload
+        sweep = {}
+        for k, mma in ((3, "f32"), (4, "f32"), (5, "f32"), (4, "bf16"), (5, "bf16")):
+            sm = Simulator(n, dtype="c64", eb=a.eb, chunk_qubits=min(20, n), k_max=k, mma=mma)
+            run(sm)
+            t1 = time.perf_counter()
+            run(sm)
+            torch.cuda.synchronize()
+            dtk = time.perf_counter() - t1
+            fk = sm.fidelity(amps_ref)
+            stk = sm.stats()
+            sm.close()
+            sweep["k%d_%s" % (k, mma)] = {"updates_per_s": G * float(1 << n) / dtk, "f_norm": fk[1],
+                                          "mfma_ops": stk["mfma_ops"], "fused_ops": stk["fused_ops"]}
+        out["mfma_sweep"] = sweep
+        del amps_ref
         out["comparators"] = {
             "c64_uncompressed_updates_per_s": G * float(1 << n) / t_plain,
             "c64_uncompressed_pass_GBps": pst["pass_bytes"] / pst["t_pass"] / 1e9 if pst["t_pass"] else None,
@@ -197,6 +253,116 @@ def main():
         }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, x, gates, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def _timed(fn, reps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, r
+
+
+def bench_host34(a):
+    """n=34 complex64 held as compressed 2^22-amplitude chunks in pinned host
+    memory (128 GiB uncompressed), eb=1e-4; random depth-40 circuit with 30%
+    two-qubit gates on qubits that cross chunks; plus GHZ-34 (exact)."""
+    from paper_2309_16979_amd import Simulator
+    from workloads import crossing_circuit, ghz
+    n, log2c, eb = 34, 22, 1e-4
+    gates = crossing_circuit(n, 40, log2c, seed=a.seed)
+    out = {"metric": "amplitude-gate updates/sec incl. codec and host link", "unit": "amplitude-gate updates/s",
+           "n_gpus": 1, "higher_is_better": True, "data": "synthetic: seeded random circuit, crossing 2q gates",
+           "dtype": "c64", "config": {"workload": "random depth 40, 30%% crossing 2q gates, n=34, complex64, "
+                                      "chunk 2^22, eb=1e-4, host-pinned store", "gates": len(gates)}}
+    with Simulator(n, dtype="c64", eb=eb, chunk_qubits=log2c, store="host", k_max=a.k) as s:
+        def run():
+            s.init_basis(0)
+            s.apply(gates)
+        run()
+        dt, _ = _timed(run, max(1, a.steps))
+        st = s.stats()
+        out.update({"value": len(gates) * float(1 << n) / dt, "s_per_apply": dt, "steps": max(1, a.steps)})
+        link = {"h2d_GBps": st["h2d_bytes"] / st["t_h2d"] / 1e9 if st["t_h2d"] else None,
+                "d2h_GBps": st["d2h_bytes"] / st["t_d2h"] / 1e9 if st["t_d2h"] else None,
+                "h2d_bytes": st["h2d_bytes"], "d2h_bytes": st["d2h_bytes"], "overlap": st["overlap"],
+                "t_kernel": st["t_kernel"], "t_total": st["t_total"], "passes": st["passes"]}
+        out["host_link"] = link
+        out["compression"] = {"ratio": st["ratio"], "compressed_bytes": st["compressed_bytes"],
+                              "max_err_all": st["max_err_all"], "err_bound": st["err_bound"],
+                              "bound_violations": st["bound_violations"]}
+    with Simulator(n, dtype="c64", eb=eb, chunk_qubits=log2c, store="host") as s:
+        s.init_basis(0)
+        t0 = time.perf_counter()
+        s.apply(ghz(n))
+        t_ghz = time.perf_counter() - t0
+        amp0 = s.amplitudes(0, 1)[0]
+        amp1 = s.amplitudes((1 << n) - 1, 1)[0]
+        out["ghz34"] = {"amp_0": [float(amp0.real), float(amp0.imag)], "amp_last": [float(amp1.real), float(amp1.imag)],
+                        "expected": 2 ** -0.5, "p_one_q0": s.prob_one(0), "s": t_ghz}
+    print(json.dumps(out), flush=True)
+
+
+def bench_adjoint22(a):
+    """Adjoint gradient, n=22 complex64, hardware-efficient ansatz (6 layers of
+    RY RZ on every qubit + CZ ring), observable sum Z_i Z_(i+1), compressed
+    checkpoints every 2 layers (uncompressed and eb=1e-4 states)."""
+    import numpy as np
+    from paper_2309_16979_amd import Simulator
+    from workloads import ansatz, ansatz_params, zz_chain
+    n, layers = 22, 6
+    gates = ansatz(n, layers)
+    params = ansatz_params(n, layers, seed=a.seed)[0]
+    masks, coeffs = zz_chain(n)
+    per_layer = len(gates) // layers
+    ck = [2 * per_layer, 4 * per_layer]
+    out = {"metric": "adjoint gradients/s", "unit": "gradients/s", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "c64", "data": "synthetic: seeded ansatz parameters",
+           "config": {"workload": "ansatz n=22, 6 layers RY RZ + CZ ring, ZZ chain, checkpoints every 2 layers",
+                      "gates": len(gates), "params": int(params.size)}}
+    for eb in (0.0, 1e-4):
+        with Simulator(n, dtype="c64", eb=eb, chunk_qubits=16) as s:
+            def run():
+                s.init_basis(0)
+                return s.adjoint(gates, params, masks, coeffs, ck)
+            run()
+            dt, (ev, grad) = _timed(run, max(1, a.steps))
+            # gate applications: forward + recompute of each segment + two sweeps of U^dagger
+            apps = 4 * len(gates)
+            out["eb=%g" % eb] = {"s_per_gradient": dt, "gradients_per_s": 1.0 / dt, "energy": ev,
+                                 "updates_per_s": apps * float(1 << n) / dt,
+                                 "grad_norm": float(np.linalg.norm(grad))}
+    out["value"] = out["eb=0"]["gradients_per_s"]
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch256(a):
+    """256 circuits of n ~ U{12..24}, depth ~ U{10..60}, complex64, eb=1e-4,
+    autotuned fusion width and tile; plus 64 ansatz parameter sets at n=18
+    through the batched adjoint."""
+    import numpy as np
+    from paper_2309_16979_amd import msv
+    from workloads import ansatz, ansatz_params, batch_circuits, zz_chain
+    circuits = [(n, g, 0) for n, g in batch_circuits(256, seed=a.seed)]
+    upd = sum(len(g) * float(1 << n) for n, g, _ in circuits)
+    msv.batch_run(circuits, dtype="c64", eb=1e-4)
+    dt, (st, _) = _timed(lambda: msv.batch_run(circuits, dtype="c64", eb=1e-4), max(1, a.steps))
+    out = {"metric": "amplitude-gate updates/sec incl. codec (batched)", "unit": "amplitude-gate updates/s",
+           "value": upd / dt, "n_gpus": 1, "higher_is_better": True, "dtype": "c64",
+           "data": "synthetic: seeded random circuits",
+           "config": {"workload": "256 circuits n in [12,24], depth 10..60, complex64, eb=1e-4, autotuned",
+                      "circuits": 256, "updates": upd},
+           "s_per_batch": dt, "kernel_launches": st["kernel_launches"], "passes": st["passes"]}
+    n, layers, sets = 18, 6, 64
+    gates = ansatz(n, layers)
+    P = ansatz_params(n, layers, seed=a.seed, count=sets)
+    masks, coeffs = zz_chain(n)
+    msv.batch_adjoint(n, gates, P[:2], masks, coeffs)
+    dt2, _ = _timed(lambda: msv.batch_adjoint(n, gates, P, masks, coeffs), 1)
+    out["batched_adjoint"] = {"sets": sets, "n": n, "s": dt2, "gradients_per_s": sets / dt2}
     print(json.dumps(out), flush=True)
 
 

@@ -100,6 +100,13 @@ typedef struct msv_stats {
                                     or 2 x 2^n x sizeof(complex) uncompressed      */
     uint64_t mfma_ops;           /* fused ops of the last apply run on the matrix
                                     cores (k >= option "mfma_min_k")              */
+    double pass_valu_ops;        /* algorithmic vector-ALU lane operations of the
+                                    pass kernels of the last apply: per amplitude,
+                                    dense k-qubit op 4*2^k (2*2^k real matrix),
+                                    diagonal 4, controlled phase 8; per codec value
+                                    and direction W + 15 (W = its block's width) */
+    double pass_mfma_flops;      /* matrix-core flops of the same passes: 8*2^k
+                                    per amplitude per fused op on MFMA            */
 } msv_stats;
 
 typedef struct msv_sim msv_sim;  /* opaque, library-owned */
