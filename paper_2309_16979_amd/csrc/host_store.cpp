@@ -217,7 +217,8 @@ std::vector<uint64_t> group_chunks(const msv_sim *s, const PassPlan &p, uint64_t
 
 // Read back a finished batch's sizes/offsets, place its chunks in the output
 // arena and queue the D2H copy.
-int finish_batch(msv_sim *s, BatchBufs &b, const std::vector<uint64_t> &chunks, int out_side, uint64_t *d2h_bytes)
+int finish_batch(msv_sim *s, BatchBufs &b, const std::vector<uint64_t> &chunks, int out_side, uint64_t *d2h_bytes,
+                 hipEvent_t t_beg = nullptr, hipEvent_t t_end = nullptr)
 {
     HostStore &h = s->hs;
     HIPCHK(s, hipEventSynchronize(b.k_done));
@@ -233,7 +234,9 @@ int finish_batch(msv_sim *s, BatchBufs &b, const std::vector<uint64_t> &chunks, 
     }
     HIPCHK(s, hipStreamWaitEvent(h.d2h, b.k_done, 0));
     HIPCHK(s, hipEventRecord(b.d2h_beg, h.d2h));
+    if (t_beg) HIPCHK(s, hipEventRecord(t_beg, h.d2h));
     HIPCHK(s, hipMemcpyAsync(h.arena[out_side].at(pos), b.out_stage.p, total, hipMemcpyDeviceToHost, h.d2h));
+    if (t_end) HIPCHK(s, hipEventRecord(t_end, h.d2h));
     HIPCHK(s, hipEventRecord(b.d2h_done, h.d2h));
     b.d2h_used = true;
     *d2h_bytes += total;
@@ -424,8 +427,15 @@ int apply_host_store(msv_sim *s, const std::vector<Prim> &prims, size_t n_gates)
         const int in_side = h.cur, out_side = h.cur ^ 1;
         arena_reset(h.arena[out_side]);
         const uint64_t n_batches = (pp.n_groups + pp.gpb - 1) / pp.gpb;
+        // timing events of every batch: H2D, kernels, D2H (begin, end each)
+        while (h.tev.size() < 6 * n_batches) {
+            hipEvent_t e;
+            HIPCHK(s, hipEventCreate(&e));
+            h.tev.push_back(e);
+        }
         std::vector<uint64_t> prev_chunks;
         int prev_set = -1;
+        uint64_t prev_bi = 0;
         for (uint64_t bi = 0; bi < n_batches; ++bi) {
             const int si = (int)(bi & 1);
             BatchBufs &b = h.bb[si];
@@ -434,12 +444,15 @@ int apply_host_store(msv_sim *s, const std::vector<Prim> &prims, size_t n_gates)
             // inputs of this buffer set were last read by the kernels of batch bi-2
             HIPCHK(s, hipStreamWaitEvent(h.h2d, b.k_done, 0));
             HIPCHK(s, hipEventRecord(b.h2d_beg, h.h2d));
+            HIPCHK(s, hipEventRecord(h.tev[6 * bi], h.h2d));
             if ((st = stage_chunks(s, in_side, b, chunks, &h2d_bytes))) return st;
+            HIPCHK(s, hipEventRecord(h.tev[6 * bi + 1], h.h2d));
             HIPCHK(s, hipEventRecord(b.h2d_done, h.h2d));
             b.h2d_used = true;
             HIPCHK(s, hipStreamWaitEvent(cs, b.h2d_done, 0));
             if (b.d2h_used) HIPCHK(s, hipStreamWaitEvent(cs, b.d2h_done, 0));
             HIPCHK(s, hipEventRecord(b.k_beg, cs));
+            HIPCHK(s, hipEventRecord(h.tev[6 * bi + 2], cs));
             MetaView v = meta_view(s, b);
             HIPCHK(s, launch_parse_chunks((const uint8_t *)b.in_stage.p, v.staged_off, v.staged_size,
                                           chunks.size(), s->log2c, (uint8_t *)b.in_W.p, (int32_t *)b.in_A.p,
@@ -466,23 +479,31 @@ int apply_host_store(msv_sim *s, const std::vector<Prim> &prims, size_t n_gates)
             if ((st = compact_batch(s, b, chunks.size(), (const uint32_t *)b.out_OFF.p,
                                     (const uint64_t *)b.out_heap.p)))
                 return st;
+            HIPCHK(s, hipEventRecord(h.tev[6 * bi + 3], cs));
             HIPCHK(s, hipEventRecord(b.k_done, cs));
             s->stats.kernel_launches += 5;
-            if (prev_set >= 0 && (st = finish_batch(s, h.bb[prev_set], prev_chunks, out_side, &d2h_bytes)))
+            if (prev_set >= 0 &&
+                (st = finish_batch(s, h.bb[prev_set], prev_chunks, out_side, &d2h_bytes, h.tev[6 * prev_bi + 4],
+                                   h.tev[6 * prev_bi + 5])))
                 return st;
             prev_chunks.swap(chunks);
             prev_set = si;
+            prev_bi = bi;
         }
-        if (prev_set >= 0 && (st = finish_batch(s, h.bb[prev_set], prev_chunks, out_side, &d2h_bytes))) return st;
+        if (prev_set >= 0 &&
+            (st = finish_batch(s, h.bb[prev_set], prev_chunks, out_side, &d2h_bytes, h.tev[6 * prev_bi + 4],
+                               h.tev[6 * prev_bi + 5])))
+            return st;
         HIPCHK(s, launch_pass_stats((const double *)h.part.p, (const uint64_t *)s->ws.pass_off.p, 1,
                                     (double *)s->ws.pass_stats.p + 3 * p, cs));
         HIPCHK(s, hipStreamSynchronize(h.d2h));
         HIPCHK(s, hipStreamSynchronize(cs));
-        for (auto &b : h.bb) {
+        HIPCHK(s, hipStreamSynchronize(h.h2d));
+        for (uint64_t bi = 0; bi < n_batches; ++bi) {
             float ms = 0.f;
-            if (b.h2d_used && hipEventElapsedTime(&ms, b.h2d_beg, b.h2d_done) == hipSuccess) t_h2d += ms * 1e-3;
-            if (b.d2h_used && hipEventElapsedTime(&ms, b.d2h_beg, b.d2h_done) == hipSuccess) t_d2h += ms * 1e-3;
-            if (hipEventElapsedTime(&ms, b.k_beg, b.k_done) == hipSuccess) t_k += ms * 1e-3;
+            if (hipEventElapsedTime(&ms, h.tev[6 * bi], h.tev[6 * bi + 1]) == hipSuccess) t_h2d += ms * 1e-3;
+            if (hipEventElapsedTime(&ms, h.tev[6 * bi + 2], h.tev[6 * bi + 3]) == hipSuccess) t_k += ms * 1e-3;
+            if (hipEventElapsedTime(&ms, h.tev[6 * bi + 4], h.tev[6 * bi + 5]) == hipSuccess) t_d2h += ms * 1e-3;
             (void)hipGetLastError();
         }
         h.cur = out_side;
@@ -612,6 +633,7 @@ void host_store_free(msv_sim *s)
         for (hipEvent_t e : {b.h2d_beg, b.h2d_done, b.k_beg, b.k_done, b.d2h_beg, b.d2h_done})
             if (e) (void)hipEventDestroy(e);
     }
+    for (hipEvent_t e : h.tev) (void)hipEventDestroy(e);
     dev_free(s, h.zero_blob);
     dev_free(s, h.part);
     dev_free(s, h.plain);

@@ -62,6 +62,7 @@ struct HostStore {
     DevMem zero_blob, part, plain;
     hipStream_t h2d = nullptr, d2h = nullptr;
     uint64_t cap_chunks = 0;   // chunks per batch buffer
+    std::vector<hipEvent_t> tev;   // timing events, 6 per batch of a pass
     bool ready = false;
 };
 
