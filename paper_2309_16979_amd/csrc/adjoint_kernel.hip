@@ -21,10 +21,10 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(PassGeom geo, Adjoint
     constexpr int NSB = 2 * NAB;
     constexpr int NW = kThreads / 64;
 
-    __shared__ T pre[TILE];
-    __shared__ T pim[TILE];
-    __shared__ T lre[TILE];
-    __shared__ T lim[TILE];
+    __shared__ __attribute__((aligned(16))) T pre[TILE];
+    __shared__ __attribute__((aligned(16))) T pim[TILE];
+    __shared__ __attribute__((aligned(16))) T lre[TILE];
+    __shared__ __attribute__((aligned(16))) T lim[TILE];
     __shared__ uint64_t sG[NAB];
     __shared__ uint32_t sW[NSB];
     __shared__ int32_t sA[NSB];

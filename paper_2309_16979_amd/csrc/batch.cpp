@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <thread>
 
 #include "internal.h"
 
@@ -67,6 +68,7 @@ int calibrate(bool is_double, hipStream_t stream)
     struct G { msv_sim *s; ~G() { msv_destroy(s); } } guard{s};
     if ((st = msv_set_error_bound(s, 1e-5))) return st;
     if ((st = msv_set_option(s, "time_passes", 1))) return st;
+    if ((st = msv_set_option(s, "mfma_min_k", 6))) return st;   // the batched kernels use the vector ALU
     if (stream) msv_set_stream(s, stream);
     // one pass that only touches qubit 0: the cost of the pass itself
     for (int tb = 10; tb <= 12; ++tb) {
@@ -174,6 +176,51 @@ extern "C" int msv_batch_run(const msv_circuit *circuits, size_t count, int dtyp
     const bool dbl = dtype == MSV_C128;
     const bool tune = !opts || opts->autotune;
     const auto t0 = std::chrono::steady_clock::now();
+    // One device allocation holds every circuit's store (bump allocation;
+    // released after the simulators).
+    struct Arena {
+        void *base = nullptr;
+        size_t cap = 0, used = 0;
+        ~Arena() { if (base) (void)hipFree(base); }
+        // stores come from the arena; anything else (work buffers, read-out
+        // staging) falls back to hipMalloc and is freed individually
+        static void *alloc(size_t b, void *ctx)
+        {
+            Arena *a = (Arena *)ctx;
+            const size_t off = (a->used + 255) & ~(size_t)255;
+            if (off + b <= a->cap) {
+                a->used = off + b;
+                return (uint8_t *)a->base + off;
+            }
+            void *p = nullptr;
+            if (hipMalloc(&p, b) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+            return p;
+        }
+        static void release(void *p, void *ctx)
+        {
+            Arena *a = (Arena *)ctx;
+            const uint8_t *q = (const uint8_t *)p, *b0 = (const uint8_t *)a->base;
+            if (p && !(q >= b0 && q < b0 + a->cap)) (void)hipFree(p);
+        }
+    } arena;
+    {
+        size_t total = 1 << 20;
+        for (size_t i = 0; i < count; ++i) {
+            const int nq = circuits[i].n_qubits;
+            if (nq < 8 || nq > 30) return fail_global(MSV_E_ARG, "circuit qubits must be in [8, 30]");
+            const uint64_t nblk = 2ull << (nq - 6);
+            total += 2 * (((nblk + 255) & ~255ull) + 2 * ((4 * nblk + 255) & ~255ull) + (8ull << nq)) + 4096;
+        }
+        if (hipMalloc(&arena.base, total) != hipSuccess) {
+            (void)hipGetLastError();
+            arena.base = nullptr;
+            return fail_global(MSV_E_NOMEM, "batch store allocation failed");
+        }
+        arena.cap = total;
+    }
     struct Sims {
         std::vector<msv_sim *> v;
         ~Sims() { for (auto *s : v) msv_destroy(s); }
@@ -184,38 +231,55 @@ extern "C" int msv_batch_run(const msv_circuit *circuits, size_t count, int dtyp
     struct SG { hipStream_t s; ~SG() { (void)hipStreamDestroy(s); } } sg{stream};
     // per circuit: simulator state, plan
     std::vector<std::vector<Pass>> plans(count);
+    std::vector<std::vector<Prim>> prims(count);
     std::vector<int> tbs(count), ks(count);
     std::string err;
     int st;
     for (size_t i = 0; i < count; ++i) {
         const msv_circuit &c = circuits[i];
-        if (c.n_qubits < 8 || c.n_qubits > 30 || (c.n_gates && !c.gates))
-            return fail_global(MSV_E_ARG, "circuit qubits must be in [8, 30]");
-        std::vector<Prim> prims(c.n_gates);
+        if (c.n_gates && !c.gates) return fail_global(MSV_E_ARG, "null gate list");
+        prims[i].resize(c.n_gates);
         for (size_t k = 0; k < c.n_gates; ++k) {
-            if ((st = gate_to_prim(c.gates[k], c.n_qubits, false, prims[k], err)))
+            if ((st = gate_to_prim(c.gates[k], c.n_qubits, false, prims[i][k], err)))
                 return fail_global(st, ("circuit gate: " + err).c_str());
-            prims[k].gate = k;
+            prims[i][k].gate = k;
         }
         msv_sim *s = nullptr;
         if ((st = msv_create(c.n_qubits, dtype, &s))) return st;
         sims.v.push_back(s);
         msv_set_stream(s, stream);
+        if ((st = msv_set_device_allocator(s, &Arena::alloc, &Arena::release, &arena))) return st;
         if ((st = msv_set_error_bound(s, eb))) return st;
         if ((st = msv_set_chunk_qubits(s, std::min(c.n_qubits, 20)))) return st;
-        if (tune) {
-            if ((st = autotune(dbl, stream, prims, c.n_qubits, &ks[i], &tbs[i], &plans[i]))) return st;
-        } else {
-            PlanOptions o;
-            o.n = c.n_qubits;
-            o.k_max = std::max(1, std::min(5, opts->k_max));
-            o.tb = opts->log2_tile ? std::min(std::max(opts->log2_tile, 8), std::min(12, c.n_qubits))
-                                   : std::min(12, c.n_qubits);
-            ks[i] = o.k_max;
-            tbs[i] = o.tb;
-            plans[i] = plan_passes(prims, o);
-        }
         if ((st = msv_init_basis(s, c.init_basis))) return st;
+    }
+    // plans: the cost-model search runs on the host, circuits in parallel
+    if (tune && (st = calibrate(dbl, stream))) return st;
+    {
+        const unsigned nt = std::max(1u, std::min<unsigned>(16, std::thread::hardware_concurrency()));
+        std::vector<int> status(count, MSV_OK);
+        auto work = [&](unsigned t) {
+            for (size_t i = t; i < count; i += nt) {
+                const int nq = circuits[i].n_qubits;
+                if (tune) {
+                    status[i] = autotune(dbl, stream, prims[i], nq, &ks[i], &tbs[i], &plans[i]);
+                } else {
+                    PlanOptions o;
+                    o.n = nq;
+                    o.k_max = std::max(1, std::min(5, opts->k_max));
+                    o.tb = opts->log2_tile ? std::min(std::max(opts->log2_tile, 8), std::min(12, nq)) : std::min(12, nq);
+                    ks[i] = o.k_max;
+                    tbs[i] = o.tb;
+                    plans[i] = plan_passes(prims[i], o);
+                }
+            }
+        };
+        std::vector<std::thread> pool;
+        for (unsigned t = 1; t < nt; ++t) pool.emplace_back(work, t);
+        work(0);
+        for (auto &th : pool) th.join();
+        for (size_t i = 0; i < count; ++i)
+            if (status[i] != MSV_OK) return status[i];
     }
     // lower every circuit's plan into one op buffer and one pool
     std::vector<OpDesc> ops;
@@ -229,6 +293,7 @@ extern "C" int msv_batch_run(const msv_circuit *circuits, size_t count, int dtyp
         o.n = circuits[i].n_qubits;
         o.tb = tbs[i];
         o.k_max = ks[i];
+        o.segments = true;
         const size_t op0 = ops.size();
         pool_off[i] = dbl ? pd.size() / 2 : pf.size() / 2;
         std::vector<OpDesc> oi;
@@ -249,20 +314,21 @@ extern "C" int msv_batch_run(const msv_circuit *circuits, size_t count, int dtyp
     // items, level by level and tile size by tile size; states ping-pong
     std::vector<BatchItem> items;
     std::vector<uint64_t> prefix;
-    struct Launch { int tb; size_t first, count; uint64_t tiles; size_t prefix0; };
+    struct Launch { int tb; size_t first, count; uint64_t tiles; size_t prefix0; int max_k; };
     std::vector<Launch> launches;
     std::vector<int> cur(count, 0);
     std::vector<uint64_t> part_off;   // per item: first per-tile triple
     uint64_t part_total = 0;
     for (size_t l = 0; l < max_levels; ++l) {
         for (int tb = 8; tb <= 12; ++tb) {
-            Launch L{tb, items.size(), 0, 0, prefix.size()};
+            Launch L{tb, items.size(), 0, 0, prefix.size(), 0};
             uint64_t acc = 0;
             for (size_t i = 0; i < count; ++i) {
                 if (tbs[i] != tb || l >= geoms[i].size()) continue;
                 msv_sim *s = sims.v[i];
                 BatchItem it{};
                 it.geo = geoms[i][l];
+                L.max_k = std::max(L.max_k, (int)it.geo.max_k);
                 it.buf.in = s->st[cur[i]].view();
                 it.buf.out = s->st[cur[i] ^ 1].view();
                 it.buf.inv_step = s->inv_step();
@@ -329,7 +395,7 @@ extern "C" int msv_batch_run(const msv_circuit *circuits, size_t count, int dtyp
     struct EG { hipEvent_t a, b; ~EG() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } eg{e0, e1};
     (void)hipEventRecord(e0, stream);
     for (const Launch &L : launches) {
-        hipError_t e = launch_batch_pass(dbl, L.tb, (const BatchItem *)d_items.p + L.first,
+        hipError_t e = launch_batch_pass(dbl, L.tb, L.max_k, (const BatchItem *)d_items.p + L.first,
                                          (const uint64_t *)d_prefix.p + L.prefix0, (int)L.count, L.tiles, stream);
         if (e != hipSuccess) return hip_fail(nullptr, e, "launch_batch_pass");
     }

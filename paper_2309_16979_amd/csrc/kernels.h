@@ -56,11 +56,12 @@ struct BatchItem {
     PassBuffers buf;
 };
 
-// Run every item's pass in one launch of sum(n_tiles) workgroups;
+// Run every item's pass in one launch of sum(n_tiles) workgroups (max_k: the
+// widest dense op of any item, selects the kernel variant);
 // prefix[i] = first workgroup of item i (prefix[0] = 0). All items share tb
 // and the compressed device layout.
-hipError_t launch_batch_pass(bool is_double, int tb, const BatchItem *items, const uint64_t *prefix, int n_items,
-                             uint64_t total_tiles, hipStream_t stream);
+hipError_t launch_batch_pass(bool is_double, int tb, int max_k, const BatchItem *items, const uint64_t *prefix,
+                             int n_items, uint64_t total_tiles, hipStream_t stream);
 
 hipError_t launch_adjoint_pass(bool is_double, bool compressed, const PassGeom &geo, const AdjointBuffers &buf,
                                hipStream_t stream);

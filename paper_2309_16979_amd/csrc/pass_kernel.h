@@ -19,15 +19,18 @@
 
 namespace msv {
 
+// One tile of a pass: decode -> ops -> encode, then the workgroup's FP64
+// statistics into part[3 pidx ..]. Shared by the single-state pass kernel and
+// the batched kernel.
 template <typename T, int TB, bool LOADC, bool STOREC, int KMAX, int MF>
-__global__ __launch_bounds__(kThreads, (KMAX <= 3 && TB <= 12) ? 4 : 2) void pass_kernel(PassGeom geo, PassBuffers buf)
+__device__ __forceinline__ void pass_tile(const PassGeom &geo, const PassBuffers &buf, uint64_t tile, uint64_t pidx)
 {
     constexpr int TILE = 1 << TB;
     constexpr int NAB = TILE >> 6;   // 64-amplitude blocks per tile
     constexpr int NSB = 2 * NAB;     // stream blocks (re + im planes)
     constexpr int NW = kThreads / 64;
 
-    __shared__ T samp[2 * TILE];   // re plane, then im plane
+    __shared__ __attribute__((aligned(16))) T samp[2 * TILE];   // re plane, then im plane
     T *const sre = samp, *const sim = samp + TILE;
     __shared__ uint64_t sG[NAB];
     __shared__ uint32_t sW[NSB];
@@ -38,7 +41,6 @@ __global__ __launch_bounds__(kThreads, (KMAX <= 3 && TB <= 12) ? 4 : 2) void pas
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform for the compiler
-    const uint64_t tile = geo.tile_begin + blockIdx.x;
     const uint64_t base = tile_base(geo, tile);
     tile_blocks<TB>(geo, base, sG);
     __syncthreads();
@@ -77,10 +79,20 @@ __global__ __launch_bounds__(kThreads, (KMAX <= 3 && TB <= 12) ? 4 : 2) void pas
         double a = 0.0, e = 0.0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) { a += sred[w]; e = fmax(e, sred[NW + w]); }
-        buf.part[3 * blockIdx.x] = a;
-        buf.part[3 * blockIdx.x + 1] = e;
-        buf.part[3 * blockIdx.x + 2] = (double)words;
+        buf.part[3 * pidx] = a;
+        buf.part[3 * pidx + 1] = e;
+        buf.part[3 * pidx + 2] = (double)words;
     }
+}
+
+// Register cap: four waves per SIMD for the common variants (LDS allows four
+// workgroups of 2^12 complex64 amplitudes per CU), two for the rest.
+template <int TB, int KMAX> struct PassOccupancy { static constexpr int waves = (KMAX <= 3 && TB <= 12) ? 4 : 2; };
+
+template <typename T, int TB, bool LOADC, bool STOREC, int KMAX, int MF>
+__global__ __launch_bounds__(kThreads, (PassOccupancy<TB, KMAX>::waves)) void pass_kernel(PassGeom geo, PassBuffers buf)
+{
+    pass_tile<T, TB, LOADC, STOREC, KMAX, MF>(geo, buf, geo.tile_begin + blockIdx.x, blockIdx.x);
 }
 
 template <typename T, int TB, int KMAX, int MF>
