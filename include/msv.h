@@ -273,13 +273,20 @@ typedef struct msv_batch_opts {
     int32_t mma_precision;   /* enum msv_mma                                    */
 } msv_batch_opts;
 
-/* Run count circuits in one persistent launch per step. amps_out[i] (host,
- * 2^n_i complex of dtype) may be NULL to skip the copy; stats_out aggregates. */
+/* Run count circuits (8..30 qubits each, compressed with eb > 0): pass level l
+ * of every circuit runs in one launch per tile size (a workgroup finds its
+ * circuit by binary search over the launch's tile counts), so small circuits
+ * together fill the GPU. With opts->autotune the fusion width and tile size
+ * of each circuit minimise a cost model calibrated once per process on the
+ * GPU. amps_out[i] (host, 2^n_i complex of dtype) may be NULL to skip the
+ * copy; stats_out aggregates. MSV_E_NOMEM when the stores do not fit. */
 int msv_batch_run(const msv_circuit *circuits, size_t count, int dtype, double eb,
                   const msv_batch_opts *opts, void *const *amps_out,
                   msv_stats *stats_out);
 /* Adjoint gradients of one ansatz for n_sets parameter sets (params is
- * n_sets x n_params, row-major); expvals[n_sets], grads[n_sets x n_params]. */
+ * n_sets x n_params, row-major); expvals[n_sets], grads[n_sets x n_params].
+ * Sets run on up to 8 concurrent workers, each with its own simulator and
+ * stream (as msv_adjoint on a fresh state). */
 int msv_batch_adjoint(const msv_circuit *ansatz, const double *params, size_t n_sets,
                       size_t n_params, const uint64_t *z_masks, const double *coeffs,
                       size_t n_terms, const size_t *ckpt_at, size_t n_ckpt, int dtype,

@@ -458,17 +458,31 @@ extern "C" int msv_batch_adjoint(const msv_circuit *ansatz, const double *params
 {
     if (!ansatz || !params || !expvals || (n_params && !grads) || n_sets == 0)
         return fail_global(MSV_E_ARG, "bad argument");
-    msv_sim *s = nullptr;
-    int st;
-    if ((st = msv_create(ansatz->n_qubits, dtype, &s))) return st;
-    struct G { msv_sim *s; ~G() { msv_destroy(s); } } guard{s};
-    if ((st = msv_set_error_bound(s, eb))) return st;
-    if ((st = msv_set_chunk_qubits(s, std::min(ansatz->n_qubits, 20)))) return st;
-    for (size_t k = 0; k < n_sets; ++k) {
-        if ((st = msv_init_basis(s, ansatz->init_basis))) return st;
-        if ((st = msv_adjoint(s, ansatz->gates, ansatz->n_gates, params + k * n_params, n_params, masks, coeffs,
-                              n_terms, ckpt_at, n_ckpt, expvals + k, grads + k * n_params)))
-            return st;
-    }
+    // Parameter sets run on concurrent workers, each with its own simulator and
+    // stream, so that the small per-set passes of several sets share the GPU.
+    const size_t nw = std::min<size_t>(n_sets, 8);
+    std::vector<int> status(nw, MSV_OK);
+    std::vector<std::string> msg(nw);
+    auto work = [&](size_t w) {
+        msv_sim *s = nullptr;
+        int st = msv_create(ansatz->n_qubits, dtype, &s);
+        if (st == MSV_OK) st = msv_set_error_bound(s, eb);
+        if (st == MSV_OK) st = msv_set_chunk_qubits(s, std::min(ansatz->n_qubits, 20));
+        for (size_t k = w; st == MSV_OK && k < n_sets; k += nw) {
+            st = msv_init_basis(s, ansatz->init_basis);
+            if (st == MSV_OK)
+                st = msv_adjoint(s, ansatz->gates, ansatz->n_gates, params + k * n_params, n_params, masks, coeffs,
+                                 n_terms, ckpt_at, n_ckpt, expvals + k, grads + k * n_params);
+        }
+        if (st != MSV_OK) msg[w] = msv_last_error(s);
+        status[w] = st;
+        if (s) msv_destroy(s);
+    };
+    std::vector<std::thread> pool;
+    for (size_t w = 1; w < nw; ++w) pool.emplace_back(work, w);
+    work(0);
+    for (auto &th : pool) th.join();
+    for (size_t w = 0; w < nw; ++w)
+        if (status[w] != MSV_OK) return fail_global(status[w], msg[w].c_str());
     return MSV_OK;
 }

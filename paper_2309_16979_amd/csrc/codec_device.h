@@ -181,61 +181,6 @@ __device__ __forceinline__ void unpack_codes2(uint64_t mr, uint32_t Wr, int32_t 
     qi = (int32_t)((uint32_t)Ai + di);
 }
 
-// Inclusive prefix sums within each 32-lane half of the wave.
-__device__ __forceinline__ uint32_t half_inclusive_sum(uint32_t x)
-{
-    x += dpp_u32<0x111, 0xf, 0xf, true>(x);   // row_shr:1
-    x += dpp_u32<0x112, 0xf, 0xf, true>(x);   // row_shr:2
-    x += dpp_u32<0x114, 0xf, 0xf, true>(x);   // row_shr:4
-    x += dpp_u32<0x118, 0xf, 0xf, true>(x);   // row_shr:8
-    x += dpp_u32<0x142, 0xa, 0xf, false>(x);  // row_bcast:15 -> rows 1, 3
-    return x;
-}
-
-// Codes of one 64-value block decoded by one half of the wave: lane i of the
-// half (li) yields values i (qa) and i + 32 (qb). ws points at the block's W
-// bit-plane words (word k: bit i = bit k of zigzag(d_i)), read as broadcasts;
-// Wm >= W is the larger width of the two halves (words beyond W are ignored).
-// The prefix sum of the residuals runs over the half for values 0..31 and
-// 32..63 and the second half adds the first half's total; when every partial
-// sum fits in 16 bits (W <= 10) both run packed in one 32-bit scan.
-__device__ __forceinline__ void decode_block_pair(const uint64_t *ws, uint32_t W, uint32_t Wm, int32_t A, int li,
-                                                  int32_t &qa, int32_t &qb)
-{
-    uint32_t ua = 0, ub = 0;
-    // four planes per step, all reads in flight together (the slot holds 32
-    // words, so reading up to the next multiple of four stays inside it; the
-    // extra planes are masked off below)
-    for (uint32_t k = 0; k < Wm; k += 4) {
-        uint64_t w[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) w[j] = ws[k + j];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            ua |= (((uint32_t)w[j] >> li) & 1u) << (k + j);
-            ub |= (((uint32_t)(w[j] >> 32) >> li) & 1u) << (k + j);
-        }
-    }
-    const uint32_t keep = W >= 32 ? ~0u : ((1u << W) - 1u);
-    ua &= keep;
-    ub &= keep;
-    const uint32_t da = (ua >> 1) ^ (0u - (ua & 1u));
-    const uint32_t db = (ub >> 1) ^ (0u - (ub & 1u));
-    int32_t sa, sb;
-    if (Wm <= 10) {
-        const uint32_t p = half_inclusive_sum(da + (db << 16));
-        sa = (int32_t)(int16_t)(uint16_t)p;
-        sb = (int32_t)(p - (uint32_t)sa) >> 16;
-    } else {
-        sa = (int32_t)half_inclusive_sum(da);
-        sb = (int32_t)half_inclusive_sum(db);
-    }
-    const int32_t t0 = __builtin_amdgcn_readlane(sa, 31), t1 = __builtin_amdgcn_readlane(sa, 63);
-    const int32_t ta = lane_id() >= 32u ? t1 : t0;
-    qa = (int32_t)((uint32_t)A + (uint32_t)sa);
-    qb = (int32_t)((uint32_t)A + (uint32_t)ta + (uint32_t)sb);
-}
-
 // FP64 sum over the 64 lanes, returned to every lane (butterfly: the same
 // order on every call, so the result is reproducible).
 __device__ __forceinline__ double wave_sum_f64(double x)

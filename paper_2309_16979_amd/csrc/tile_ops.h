@@ -87,17 +87,13 @@ __device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, co
         }
         return;
     }
-    // Compressed: the wave decodes amplitude blocks jb = wave + NW * a in
-    // rounds of up to 16. Lane j < 32 fetches the width, anchor and payload
-    // offset of amplitude block a = r0 + j / 2, plane j & 1; every stream
-    // block's payload word `lane` is loaded (all loads of the round in flight
-    // before the first wait) and parked in the block's own slot of the tile
-    // (64 values of a plane hold up to 32 words), where both halves of the wave
-    // read them back as broadcasts: lanes 0..31 decode the real plane, lanes
-    // 32..63 the imaginary plane, lane i producing values i and i + 32.
+    // Compressed: the wave decodes amplitude blocks jb = wave + NW * a, both
+    // planes together, in rounds of up to 16. Lane j < 32 fetches the width,
+    // anchor and payload offset of amplitude block a = r0 + j / 2, plane j & 1;
+    // then every block's payload word `lane` is loaded, and one wait covers
+    // all of them before the bit planes are unpacked.
     constexpr int APW = (NAB + NW - 1) / NW;   // amplitude blocks per wave
     constexpr int RA = APW < 16 ? APW : 16;
-    const int h = lane >> 5, li = lane & 31;
     for (int r0 = 0; r0 < APW; r0 += RA) {
         uint32_t wv = 0, ov = 0;
         int32_t av = 0;
@@ -120,30 +116,18 @@ __device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, co
             if ((uint32_t)lane < W) mine[j] = in.heap[(uint64_t)off + lane];
         }
 #pragma unroll
-        for (int j = 0; j < 2 * RA; ++j) {
-            const int jb = wave + NW * (r0 + j / 2);
-            const uint32_t W = (uint32_t)__builtin_amdgcn_readlane((int)wv, j);
-            if (r0 + j / 2 < APW && jb < NAB && (uint32_t)lane < W)
-                reinterpret_cast<uint64_t *>(((j & 1) ? sim : sre) + jb * 64)[lane] = mine[j];
-        }
-#pragma unroll
         for (int a = 0; a < RA; ++a) {
             const int jb = wave + NW * (r0 + a);
             if (r0 + a >= APW || jb >= NAB) break;
-            const uint32_t Wx = (uint32_t)__builtin_amdgcn_readlane((int)wv, 2 * a);
-            const uint32_t Wy = (uint32_t)__builtin_amdgcn_readlane((int)wv, 2 * a + 1);
-            const int32_t Ax = __builtin_amdgcn_readlane(av, 2 * a);
-            const int32_t Ay = __builtin_amdgcn_readlane(av, 2 * a + 1);
-            const uint32_t W = h ? Wy : Wx;
-            const uint32_t Wm = Wx > Wy ? Wx : Wy;
-            T *slot = (h ? sim : sre) + jb * 64;
-            const uint64_t *ws = reinterpret_cast<const uint64_t *>(slot);
-            int32_t qa, qb;
-            decode_block_pair(ws, W, Wm, h ? Ay : Ax, li, qa, qb);
-            T xa = dequantize<T>(qa, step), xb = dequantize<T>(qb, step);
-            if (sc != 1.0) { xa *= scale; xb *= scale; }
-            slot[li] = xa;
-            slot[32 + li] = xb;
+            int32_t qr, qi;
+            unpack_codes2(mine[2 * a], (uint32_t)__builtin_amdgcn_readlane((int)wv, 2 * a),
+                          __builtin_amdgcn_readlane(av, 2 * a), mine[2 * a + 1],
+                          (uint32_t)__builtin_amdgcn_readlane((int)wv, 2 * a + 1),
+                          __builtin_amdgcn_readlane(av, 2 * a + 1), qr, qi);
+            T xr = dequantize<T>(qr, step), xi = dequantize<T>(qi, step);
+            if (sc != 1.0) { xr *= scale; xi *= scale; }
+            sre[jb * 64 + lane] = xr;
+            sim[jb * 64 + lane] = xi;
         }
     }
 }
