@@ -58,7 +58,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip comparison runs outside the timed loop")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", default="qft28", choices=["qft28", "host34", "adjoint22", "batch256"])
+    ap.add_argument("--workload", default="qft28",
+                    choices=["qft28", "random20", "host34", "adjoint22", "batch256"])
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy (scales the HBM byte counters)")
     return ap.parse_args()
@@ -135,7 +136,8 @@ def main():
         print(json.dumps({"copy_probe_bytes": src.numel() * 4}))
         return
     if a.workload != "qft28":
-        {"host34": bench_host34, "adjoint22": bench_adjoint22, "batch256": bench_batch256}[a.workload](a)
+        {"random20": bench_random20, "host34": bench_host34, "adjoint22": bench_adjoint22,
+         "batch256": bench_batch256}[a.workload](a)
         return
     n = a.n
     x, gates = qft_plus_random(n, 100, seed=a.seed)
@@ -264,6 +266,47 @@ def _timed(fn, reps):
         r = fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / reps, r
+
+
+def bench_random20(a):
+    """n=20 complex128, random depth-20 circuit from |0>, 2^14-amplitude
+    chunks: uncompressed and eb=1e-4; the FP64 oracle on all host threads and
+    on one thread (the whole circuit), and the fidelity of each GPU run."""
+    import numpy as np
+    import oracle
+    from paper_2309_16979_amd import Simulator
+    from workloads import random_circuit
+    n = 20
+    gates = random_circuit(n, 20, seed=a.seed)
+    out = {"metric": "amplitude-gate updates/sec incl. codec", "unit": "amplitude-gate updates/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "c128", "data": "synthetic: seeded random circuit",
+           "config": {"workload": "random depth 20, n=20, complex128, chunk 2^14", "gates": len(gates)}}
+    t0 = time.perf_counter()
+    ref = oracle.simulate(n, gates, 0)
+    t_or = time.perf_counter() - t0
+    for eb in (0.0, 1e-4):
+        with Simulator(n, dtype="c128", eb=eb, chunk_qubits=14) as s:
+            def run():
+                s.init_basis(0)
+                s.apply(gates)
+            run()
+            dt, _ = _timed(run, max(5, a.steps))
+            st = s.stats()
+            f = s.fidelity(ref)
+            out["eb=%g" % eb] = {"updates_per_s": len(gates) * float(1 << n) / dt, "s_per_apply": dt,
+                                 "passes": st["passes"], "ratio": st["ratio"], "f_raw": f[0], "f_norm": f[1],
+                                 "max_err_all": st["max_err_all"], "bound_violations": st["bound_violations"]}
+    out["value"] = out["eb=0.0001"]["updates_per_s"]
+    out["oracle"] = {"threads": int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count(),
+                     "updates_per_s": len(gates) * float(1 << n) / t_or}
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    import subprocess
+    code = ("import sys,time; sys.path.insert(0, %r); import oracle; from workloads import random_circuit; "
+            "g = random_circuit(20, 20, seed=%d); t = time.perf_counter(); oracle.simulate(20, g, 0); "
+            "print(len(g) * 2.0 ** 20 / (time.perf_counter() - t))" % (ROOT, a.seed))
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+    out["oracle_1_thread_updates_per_s"] = float(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 else None
+    print(json.dumps(out), flush=True)
 
 
 def bench_host34(a):
