@@ -157,7 +157,7 @@ int msv_set_fusion(msv_sim *sim, int k_max, int mma_precision);
  *   "batch_chunks" host store: chunks per streamed batch (0 = automatic)
  *   "time_passes"  1 = time every pass kernel with events (msv_stats.t_pass)
  *   "lookahead"    gates the planner scans past a deferred gate to pull
- *                  commuting gates into the current pass (default 64, 0 = none)
+ *                  commuting gates into the current pass (default 1024, 0 = none)
  *   "segments"     1 (default) = run runs of 1-2 qubit dense ops, diagonals and
  *                  controlled phases on per-thread registers (tiles of 2^10 ..
  *                  2^13), one LDS round trip per run; 0 = one per op

@@ -1,8 +1,9 @@
 // Launch of the fused streamed pass kernel (pass_kernel.h): picks the variant
-// for the state's type and the pass's matrix-core mode.
+// for the state's type and the pass's matrix-core mode. The variants are
+// instantiated in pass_f32*.hip / pass_f64*.hip.
 #include <hip/hip_runtime.h>
 
-#include "pass_kernel.h"
+#include "kernels.h"
 
 namespace msv {
 

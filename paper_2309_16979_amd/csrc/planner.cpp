@@ -371,51 +371,71 @@ std::vector<Pass> plan_passes(const std::vector<Prim> &prims, const PlanOptions 
 {
     std::vector<Pass> passes;
     const int tb = o.tb;
+    // Qubit masks: q (the dense / diagonal qubits) and support (q and control).
+    std::vector<uint64_t> qm(prims.size()), sm(prims.size());
+    for (size_t i = 0; i < prims.size(); ++i) {
+        uint64_t m = 0;
+        for (int q : prims[i].q) m |= 1ull << q;
+        qm[i] = m;
+        sm[i] = prims[i].ctrl >= 0 ? m | (1ull << prims[i].ctrl) : m;
+    }
     // Gates not yet placed, in list order. Each pass takes every gate that
     // fits the tile and commutes with all gates deferred before it in this
     // pass, scanning a bounded window ahead of the first deferred gate.
+    // commute(p, d) for every deferred d (see commute) reduces to unions of
+    // the deferred gates' masks: a diagonal p must avoid the targets of the
+    // deferred dense gates; a dense p must avoid their supports and the
+    // qubits of the deferred diagonals.
     std::vector<size_t> rest(prims.size());
     for (size_t i = 0; i < prims.size(); ++i) rest[i] = i;
     const size_t window = (size_t)std::max(0, o.lookahead);
+    const uint64_t low6 = o.n >= 6 ? 63ull : ((1ull << o.n) - 1);
     while (!rest.empty()) {
-        std::vector<int> L = {0, 1, 2, 3, 4, 5};
-        L.resize(std::min(6, o.n));
+        uint64_t L = low6;
+        uint64_t nd_q = 0, nd_s = 0, d_q = 0;   // deferred: dense targets, dense supports, diagonal qubits
+        bool def_special = false;               // a probe / observable was deferred
         std::vector<size_t> take, defer;
         size_t scanned_after_defer = 0;
         size_t pos = 0;
         for (; pos < rest.size(); ++pos) {
-            const Prim &p = prims[rest[pos]];
+            const size_t i = rest[pos];
+            const Prim &p = prims[i];
             if (!defer.empty() && (p.probe || p.obs || ++scanned_after_defer > window)) break;
+            uint64_t U = L;
             bool fits = true;
-            std::vector<int> U = L;
             if (!(p.diag || p.obs || p.probe) || (p.probe && !p.diag)) {
-                U = unite(L, p.q);
-                fits = (int)U.size() <= tb;
+                U = L | qm[i];
+                fits = __builtin_popcountll(U) <= tb;
             }
             bool ok = fits;
-            for (size_t d : defer)
-                if (ok && !commute(p, prims[d])) ok = false;
+            if (ok && !defer.empty()) {
+                if (def_special || p.probe || p.obs) ok = false;
+                else if (p.diag) ok = (qm[i] & nd_q) == 0;
+                else ok = (sm[i] & nd_s) == 0 && (qm[i] & d_q) == 0;
+            }
             if (ok) {
-                take.push_back(rest[pos]);
+                take.push_back(i);
                 L = U;
             } else {
-                defer.push_back(rest[pos]);
+                defer.push_back(i);
+                if (p.probe || p.obs) def_special = true;
+                else if (p.diag) d_q |= qm[i];
+                else { nd_q |= qm[i]; nd_s |= sm[i]; }
             }
         }
         if (take.empty()) {   // cannot happen for tb >= 8; keep progress regardless
             take.push_back(rest[0]);
             defer.erase(defer.begin());
-            L = unite(L, prims[rest[0]].q);
+            L |= qm[rest[0]];
         }
         std::vector<size_t> next = defer;
         next.insert(next.end(), rest.begin() + pos, rest.end());
         rest.swap(next);
         // fill the tile with the lowest remaining qubits
-        for (int q = 0; (int)L.size() < tb && q < o.n; ++q)
-            if (std::find(L.begin(), L.end(), q) == L.end()) L.push_back(q);
-        std::sort(L.begin(), L.end());
+        for (int q = 0; __builtin_popcountll(L) < tb && q < o.n; ++q) L |= 1ull << q;
         Pass ps;
-        ps.tile_q = L;
+        for (int q = 0; q < o.n; ++q)
+            if ((L >> q) & 1ull) ps.tile_q.push_back(q);
         ps.gate_begin = prims[take.front()].gate;
         ps.gate_end = prims[take.back()].gate + 1;
         Fuser f(o, ps.tile_q);

@@ -59,7 +59,7 @@ struct PlanOptions {
     int k_max = 2;
     int mfma_min_k = 6;       // dense ops with k >= this run on matrix cores
     int mma = 0;              // matrix-core mode (MmaMode); 0 keeps every dense op on the VALU
-    int lookahead = 64;       // gates scanned past the first deferred one (0 = strict order)
+    int lookahead = 1024;     // gates scanned past the first deferred one (0 = strict order)
     bool segments = false;    // group ops into register segments (pass kernels with 2^10..2^13 tiles)
 };
 

@@ -80,7 +80,7 @@ struct msv_sim {
     int batch_chunks = 0;
     int time_passes = 0;
     int autotune = 0;
-    int lookahead = 64;
+    int lookahead = 1024;
     int segments = 1;                // register segments in pass kernels
     int tuned_k = 0, tuned_tb = 0;   // last autotuner choice
     void *(*alloc)(size_t, void *) = nullptr;

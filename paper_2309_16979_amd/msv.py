@@ -232,7 +232,7 @@ def codec_decode(blob: bytes, dtype: str = "c64") -> np.ndarray:
     return out
 
 
-def plan(n: int, gates: Sequence, log2_tile: int = 12, k_max: int = 2, lookahead: int = 64):
+def plan(n: int, gates: Sequence, log2_tile: int = 12, k_max: int = 2, lookahead: int = 1024):
     """The passes and fused ops msv_apply would run (host-side planning only).
 
     Returns (n_passes, ops) where each op is a dict with keys pass, type

@@ -86,7 +86,8 @@ def _plan_unitary(n, ops):
     return U
 
 
-@pytest.mark.parametrize("n,tb,k,la", [(6, 6, 1, 0), (7, 6, 2, 64), (8, 8, 3, 0), (8, 8, 5, 64), (8, 7, 2, 8)])
+@pytest.mark.parametrize("n,tb,k,la", [(6, 6, 1, 0), (7, 6, 2, 64), (8, 8, 3, 0), (8, 8, 5, 64), (8, 7, 2, 8),
+                                      (9, 7, 2, 4096), (10, 8, 3, 1024), (10, 7, 1, 4096)])
 def test_plan_composes_to_circuit_unitary(plan, n, tb, k, la):
     gates = _mixed(n, 70, seed=n * 7 + k)
     n_passes, ops = plan(n, gates, log2_tile=tb, k_max=k, lookahead=la)
