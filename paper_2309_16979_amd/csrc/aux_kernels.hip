@@ -19,21 +19,6 @@ static __device__ __forceinline__ uint64_t bidx(const BlockStore &s, uint64_t B)
     return ((uint64_t)s.chunk_slot[B >> s.log2_nb] << s.log2_nb) | (B & nbm);
 }
 
-// Decode one 64-value stream block with the calling wave; lane i gets value i.
-template <typename T>
-static __device__ __forceinline__ T decode_one(const BlockStore &s, uint64_t B, double step)
-{
-    const uint64_t bi = bidx(s, B);
-    const uint32_t W = s.W[bi];
-    const int32_t A = s.A[bi];
-    uint64_t mine = 0;
-    if (W) {
-        const uint64_t off = s.OFF[bi];
-        if (lane_id() < W) mine = s.heap[off + lane_id()];
-    }
-    return dequantize<T>(unpack_codes(mine, W, A), step);
-}
-
 // ------------------------------------------------------------------ init
 
 template <typename T>

@@ -97,25 +97,6 @@ __device__ __forceinline__ uint64_t pack_planes(uint32_t u, uint32_t W)
     return mine;
 }
 
-// Inverse of pack_planes + prediction: code of this lane's value. `mine` is the
-// word this lane loaded (word lane, lanes >= W hold anything).
-__device__ __forceinline__ int32_t unpack_codes(uint64_t mine, uint32_t W, int32_t A)
-{
-    if (W == 0) return A;
-    const uint32_t lane = lane_id();
-    const uint32_t sh = lane & 31u;
-    const bool hi = lane >= 32u;
-    uint32_t u = 0;
-    for (uint32_t k = 0; k < W; ++k) {
-        const uint32_t lo_w = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mine, (int)k);
-        const uint32_t hi_w = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mine >> 32), (int)k);
-        const uint32_t w = hi ? hi_w : lo_w;
-        u |= ((w >> sh) & 1u) << k;
-    }
-    const uint32_t d = (u >> 1) ^ (0u - (u & 1u));
-    return (int32_t)((uint32_t)A + wave_inclusive_sum(d));
-}
-
 // Two independent inclusive prefix sums, interleaved so that each DPP step of
 // one chain fills the other's hazard slots.
 __device__ __forceinline__ void wave_inclusive_sum2(uint32_t &x, uint32_t &y)

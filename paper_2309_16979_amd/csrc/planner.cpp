@@ -334,39 +334,6 @@ struct Fuser {
 
 }  // namespace
 
-namespace {
-
-// Qubits a prim acts on non-trivially as a dense map (its targets), and all
-// qubits it reads (targets and control).
-std::vector<int> support(const Prim &p)
-{
-    std::vector<int> s = p.q;
-    if (p.ctrl >= 0) s.push_back(p.ctrl);
-    return s;
-}
-
-bool disjoint(const std::vector<int> &a, const std::vector<int> &b)
-{
-    for (int x : a)
-        if (std::find(b.begin(), b.end(), x) != b.end()) return false;
-    return true;
-}
-
-// Sufficient conditions for two gates to commute: disjoint supports; both
-// diagonal; or one diagonal acting only on qubits the other does not
-// transform (a control, or a qubit it does not touch).
-bool commute(const Prim &a, const Prim &b)
-{
-    if (a.probe || b.probe || a.obs || b.obs) return false;
-    if (disjoint(support(a), support(b))) return true;
-    if (a.diag && b.diag) return true;
-    if (a.diag) return disjoint(a.q, b.q);
-    if (b.diag) return disjoint(b.q, a.q);
-    return false;
-}
-
-}  // namespace
-
 std::vector<Pass> plan_passes(const std::vector<Prim> &prims, const PlanOptions &o)
 {
     std::vector<Pass> passes;
@@ -381,8 +348,11 @@ std::vector<Pass> plan_passes(const std::vector<Prim> &prims, const PlanOptions 
     }
     // Gates not yet placed, in list order. Each pass takes every gate that
     // fits the tile and commutes with all gates deferred before it in this
-    // pass, scanning a bounded window ahead of the first deferred gate.
-    // commute(p, d) for every deferred d (see commute) reduces to unions of
+    // pass, scanning a bounded window ahead of the first deferred gate. Two
+    // gates are taken to commute when their supports (targets and control)
+    // are disjoint, when both are diagonal, or when one is diagonal on qubits
+    // the other does not transform; probes and observables commute with
+    // nothing. Against every deferred gate at once this reduces to unions of
     // the deferred gates' masks: a diagonal p must avoid the targets of the
     // deferred dense gates; a dense p must avoid their supports and the
     // qubits of the deferred diagonals.
