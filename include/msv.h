@@ -161,6 +161,11 @@ int msv_set_fusion(msv_sim *sim, int k_max, int mma_precision);
  *   "segments"     1 (default) = run runs of 1-2 qubit dense ops, diagonals and
  *                  controlled phases on per-thread registers (tiles of 2^10 ..
  *                  2^13), one LDS round trip per run; 0 = one per op
+ *   "relabel_swaps" 1 (default) = compressed device store: a SWAP of two qubits
+ *                  >= 6 renames qubits instead of moving amplitudes (it only
+ *                  permutes 64-amplitude blocks); the last pass of the call
+ *                  writes its blocks back in the identity order. 0 = every
+ *                  SWAP runs as a 4x4 gate
  *   "autotune"     1 = choose fusion width and tile size per msv_apply from a
  *                  cost model calibrated once per process on the GPU */
 int msv_set_option(msv_sim *sim, const char *key, double value);
@@ -221,10 +226,14 @@ int msv_export_chunk(msv_sim *sim, uint64_t chunk, void *host_out, size_t cap,
  * diagonal: data = 2^k complex entries on (q0..q_{k-1});
  * controlled phase: data = [G re, G im, mu[n], lam[n]], the factor
  *        G e^{i sum mu_q b_q} (b_hub ? e^{i sum lam_q b_q} : 1).
- * tile_mask holds the pass's tile qubits. *used receives the doubles needed
- * (call with cap 0 to size buf). */
+ * tile_mask holds the pass's tile qubits. relabel = 1 plans as a compressed
+ * device-store state with option "relabel_swaps" on: SWAPs of qubits >= 6 are
+ * renamed away, later ops use the renamed qubits, and the pass that writes
+ * the identity order back ends with a record of type 4, k = 0, len = n,
+ * data = out_q[n] (the qubit stored at position q moves to position out_q[q]).
+ * *used receives the doubles needed (call with cap 0 to size buf). */
 int msv_plan_export(int n_qubits, const msv_gate *gates, size_t n_gates, int log2_tile, int k_max,
-                    int lookahead, double *buf, size_t cap, size_t *used, uint64_t *n_passes);
+                    int lookahead, int relabel, double *buf, size_t cap, size_t *used, uint64_t *n_passes);
 
 /* ---- codec on its own ---------------------------------------------------------
  * Format "MSVC" v1 for a chunk of C = 2^log2_chunk complex values:

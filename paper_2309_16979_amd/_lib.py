@@ -118,7 +118,8 @@ def load():
                            P, C.POINTER(Stats)], C.c_int),
         "msv_batch_adjoint": ([C.POINTER(Circuit), P, C.c_size_t, C.c_size_t, P, P, C.c_size_t, P,
                                C.c_size_t, C.c_int, C.c_double, P, P], C.c_int),
-        "msv_plan_export": ([C.c_int, C.POINTER(Gate), C.c_size_t, C.c_int, C.c_int, C.c_int, P, C.c_size_t,
+        "msv_plan_export": ([C.c_int, C.POINTER(Gate), C.c_size_t, C.c_int, C.c_int, C.c_int, C.c_int, P,
+                             C.c_size_t,
                              C.POINTER(C.c_size_t), C.POINTER(C.c_uint64)], C.c_int),
     }
     for name, (args, res) in sig.items():

@@ -437,6 +437,8 @@ int msv_set_option(msv_sim *s, const char *key, double v)
         s->lookahead = iv;
     } else if (!strcmp(key, "segments")) {
         s->segments = v != 0.0;
+    } else if (!strcmp(key, "relabel_swaps")) {
+        s->relabel = v != 0.0;
     } else if (!strcmp(key, "autotune")) {
         s->autotune = v != 0.0;
     } else if (!strcmp(key, "time_passes")) {
@@ -612,14 +614,22 @@ int msv_apply(msv_sim *s, const msv_gate *gates, size_t n_gates)
         o.segments = s->segments;
         o.lookahead = s->lookahead;
         std::vector<Pass> passes;
+        // compressed states live in two stores (ping-pong), so a pass may
+        // write its blocks to other positions than it read them from
+        std::vector<int> pos;
+        std::vector<Prim> renamed;
+        const bool relabel = s->relabel && s->compressed();
+        if (relabel) renamed = relabel_swaps(prims, s->n, pos);
+        const std::vector<Prim> &pl = relabel ? renamed : prims;
         if (s->autotune && s->compressed()) {
             int k = o.k_max, tb = o.tb;
-            if ((st = autotune(s->is_double(), s->stream(), prims, s->n, &k, &tb, &passes))) return st;
+            if ((st = autotune(s->is_double(), s->stream(), pl, s->n, &k, &tb, &passes))) return st;
             o.k_max = s->tuned_k = k;
             o.tb = s->tuned_tb = tb;
         } else {
-            passes = plan_passes(prims, o);
+            passes = plan_passes(pl, o);
         }
+        if (relabel) restore_order(passes, pos, o);
         size_t n_ops = 0;
         for (auto &p : passes) n_ops += p.ops.size();
         double norm = 0.0, err_last = 0.0, words = 0.0;
@@ -832,7 +842,7 @@ int msv_get_stats(msv_sim *s, msv_stats *out)
 }
 
 int msv_plan_export(int n, const msv_gate *gates, size_t n_gates, int log2_tile, int k_max, int lookahead,
-                    double *buf, size_t cap, size_t *used, uint64_t *n_passes)
+                    int relabel, double *buf, size_t cap, size_t *used, uint64_t *n_passes)
 {
     if (n < 6 || n > 40 || (n_gates && !gates) || !used || !n_passes || k_max < 1 || k_max > kMaxFuse ||
         log2_tile < kMinTileBits || log2_tile > kMaxTileBits || lookahead < 0)
@@ -849,7 +859,14 @@ int msv_plan_export(int n, const msv_gate *gates, size_t n_gates, int log2_tile,
     o.tb = std::min(log2_tile, n);
     o.k_max = k_max;
     o.lookahead = lookahead;
-    std::vector<Pass> passes = plan_passes(prims, o);
+    std::vector<int> pos;
+    std::vector<Pass> passes;
+    if (relabel) {
+        passes = plan_passes(relabel_swaps(prims, n, pos), o);
+        restore_order(passes, pos, o);
+    } else {
+        passes = plan_passes(prims, o);
+    }
     std::vector<double> out;
     for (size_t p = 0; p < passes.size(); ++p) {
         uint64_t tmask = 0;
@@ -876,6 +893,18 @@ int msv_plan_export(int n, const msv_gate *gates, size_t n_gates, int log2_tile,
             }
             out.push_back((double)d.size());
             out.insert(out.end(), d.begin(), d.end());
+        }
+        if (!passes[p].out_q.empty()) {
+            // output order record: qubit q is stored at position out_q[q]
+            out.push_back((double)p);
+            out.push_back(4.0);
+            out.push_back(0.0);
+            for (int m = 0; m < 5; ++m) out.push_back(-1.0);
+            out.push_back(0.0);
+            out.push_back((double)tmask);
+            out.push_back(-1.0);
+            out.push_back((double)n);
+            for (int q = 0; q < n; ++q) out.push_back((double)passes[p].out_q[q]);
         }
     }
     *used = out.size();

@@ -63,6 +63,8 @@ struct PassGeom {
     uint64_t n_tiles;      // tiles in this launch
     int32_t max_k;         // widest VALU dense op of the pass (selects the kernel variant)
     int32_t mma;           // matrix-core mode of the pass's OP_MFMA ops (MmaMode), 0 = none
+    int32_t out_perm;      // 1: the output stores qubit q at position out_q[q] (out_q[q] = q for q < 6)
+    uint8_t out_q[64];
 };
 
 }  // namespace msv

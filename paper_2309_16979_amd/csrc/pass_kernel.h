@@ -65,6 +65,18 @@ __device__ __forceinline__ void pass_tile(const PassGeom &geo, const PassBuffers
         __syncthreads();
     }
 
+    if (geo.out_perm) {
+        // the output order moves whole blocks: block index bit i (qubit i + 6)
+        // goes to qubit out_q[i + 6]
+        for (int jb = tid; jb < NAB; jb += kThreads) {
+            const uint64_t G = sG[jb];
+            uint64_t o = 0;
+            for (int i = 0; i < geo.n - 6; ++i) o |= ((G >> i) & 1ull) << (geo.out_q[i + 6] - 6);
+            sG[jb] = o;
+        }
+        __syncthreads();
+    }
+
     double nrm = 0.0, err = 0.0;
     const uint64_t slot = (tile - buf.slot_tile0) * (uint64_t)(32 * NSB);
     const uint32_t words = tile_store<T, TB, STOREC>(sre, sim, sG, sW, sA, sOff, buf.amps_out, buf.out, slot,

@@ -334,6 +334,42 @@ struct Fuser {
 
 }  // namespace
 
+std::vector<Prim> relabel_swaps(const std::vector<Prim> &prims, int n, std::vector<int> &pos)
+{
+    pos.resize(n);
+    for (int q = 0; q < n; ++q) pos[q] = q;
+    std::vector<Prim> out;
+    out.reserve(prims.size());
+    for (const Prim &p : prims) {
+        if (p.kind == MSV_SWAP && p.ctrl < 0 && !p.probe && !p.obs && p.q.size() == 2 && pos[p.q[0]] >= 6 &&
+            pos[p.q[1]] >= 6) {
+            std::swap(pos[p.q[0]], pos[p.q[1]]);
+            continue;
+        }
+        Prim r = p;
+        for (int &q : r.q) q = pos[q];
+        if (r.ctrl >= 0) r.ctrl = pos[r.ctrl];
+        out.push_back(std::move(r));
+    }
+    return out;
+}
+
+void restore_order(std::vector<Pass> &passes, const std::vector<int> &pos, const PlanOptions &o)
+{
+    bool ident = true;
+    for (int q = 0; q < (int)pos.size(); ++q) ident &= pos[q] == q;
+    if (ident) return;
+    if (passes.empty()) {
+        Pass ps;
+        for (int q = 0; q < o.tb; ++q) ps.tile_q.push_back(q);
+        passes.push_back(ps);
+    }
+    // the qubit stored at position pos[q] goes back to position q
+    std::vector<int> &oq = passes.back().out_q;
+    oq.assign(pos.size(), 0);
+    for (int q = 0; q < (int)pos.size(); ++q) oq[pos[q]] = q;
+}
+
 std::vector<Pass> plan_passes(const std::vector<Prim> &prims, const PlanOptions &o)
 {
     std::vector<Pass> passes;
@@ -442,6 +478,13 @@ bool lower_passes(const std::vector<Pass> &passes, const PlanOptions &o, std::ve
         g.nontile_mask = all & ~tmask;
         g.tile_begin = 0;
         g.n_tiles = 1ull << (n - tb);
+        if (!ps.out_q.empty()) {
+            g.out_perm = 1;
+            for (int q = 0; q < n; ++q) {
+                g.out_q[q] = (uint8_t)ps.out_q[q];
+                ok = ok && (q < 6 ? ps.out_q[q] == q : (ps.out_q[q] >= 6 && ps.out_q[q] < n));
+            }
+        }
         auto tpos = [&](int q) {
             for (int i = 0; i < tb; ++i)
                 if (ps.tile_q[i] == q) return i;

@@ -51,6 +51,9 @@ struct Pass {
     std::vector<int> tile_q;  // tb qubits, [0..5] = 0..5, then ascending
     std::vector<HostOp> ops;
     size_t gate_begin = 0, gate_end = 0;
+    // Non-empty: the pass stores its output with qubit q moved to position
+    // out_q[q] (a permutation that fixes 0..5: only block positions change).
+    std::vector<int> out_q;
 };
 
 struct PlanOptions {
@@ -66,6 +69,19 @@ struct PlanOptions {
 // Canonicalise one ABI gate (inverse = apply U^dagger). Returns MSV_OK or an
 // MSV_E_* code with a message.
 int gate_to_prim(const msv_gate &g, int n, bool inverse, Prim &out, std::string &err);
+
+// Qubit relabelling. A SWAP of two qubits whose current positions are both
+// >= 6 exchanges whole 64-amplitude codec blocks, so it needs no arithmetic:
+// it is dropped and every later prim is renamed to the positions the qubits
+// then occupy. Returns the renamed prims; pos[q] is the final position of
+// qubit q. The state the renamed prims produce equals the original result
+// with each qubit q stored at position pos[q].
+std::vector<Prim> relabel_swaps(const std::vector<Prim> &prims, int n, std::vector<int> &pos);
+
+// Makes the last pass store its output in the identity qubit order, given the
+// positions relabel_swaps returned; appends a pass without ops when there is
+// none. No-op when pos is the identity.
+void restore_order(std::vector<Pass> &passes, const std::vector<int> &pos, const PlanOptions &o);
 
 // Partition prims (in list order) into passes and fuse each pass's ops.
 std::vector<Pass> plan_passes(const std::vector<Prim> &prims, const PlanOptions &o);

@@ -82,6 +82,7 @@ struct msv_sim {
     int autotune = 0;
     int lookahead = 1024;
     int segments = 1;                // register segments in pass kernels
+    int relabel = 1;                 // SWAPs of block-index qubits as relabelling (compressed device store)
     int tuned_k = 0, tuned_tb = 0;   // last autotuner choice
     void *(*alloc)(size_t, void *) = nullptr;
     void (*dealloc)(void *, void *) = nullptr;

@@ -232,23 +232,28 @@ def codec_decode(blob: bytes, dtype: str = "c64") -> np.ndarray:
     return out
 
 
-def plan(n: int, gates: Sequence, log2_tile: int = 12, k_max: int = 2, lookahead: int = 1024):
+def plan(n: int, gates: Sequence, log2_tile: int = 12, k_max: int = 2, lookahead: int = 1024,
+         relabel: bool = False):
     """The passes and fused ops msv_apply would run (host-side planning only).
 
     Returns (n_passes, ops) where each op is a dict with keys pass, type
-    ("dense", "diag", "phase"), qubits, ctrl_mask, tile_mask, hub and data
-    (matrix, diagonal, or (G, mu, lam) for a controlled phase)."""
+    ("dense", "diag", "phase", "order"), qubits, ctrl_mask, tile_mask, hub and
+    data (matrix, diagonal, (G, mu, lam) for a controlled phase, or the output
+    positions out_q for an "order" record). relabel=True plans as a compressed
+    device-store state does: SWAPs of qubits >= 6 become renaming, and the
+    last pass carries an "order" record that restores the identity order."""
     Lb = load()
     arr, keep = gate_array(gates)
     used = C.c_size_t(0)
     npass = C.c_uint64(0)
-    check(Lb.msv_plan_export(n, arr, len(gates), log2_tile, k_max, lookahead, None, 0, C.byref(used),
+    rl = 1 if relabel else 0
+    check(Lb.msv_plan_export(n, arr, len(gates), log2_tile, k_max, lookahead, rl, None, 0, C.byref(used),
                              C.byref(npass)))
     buf = np.zeros(max(1, used.value))
-    check(Lb.msv_plan_export(n, arr, len(gates), log2_tile, k_max, lookahead, buf.ctypes.data, buf.size,
+    check(Lb.msv_plan_export(n, arr, len(gates), log2_tile, k_max, lookahead, rl, buf.ctypes.data, buf.size,
                              C.byref(used), C.byref(npass)))
     ops, i = [], 0
-    names = {0: "dense", 1: "diag", 3: "phase"}
+    names = {0: "dense", 1: "diag", 3: "phase", 4: "order"}
     while i < used.value:
         p_, t, k = int(buf[i]), int(buf[i + 1]), int(buf[i + 2])
         q = [int(v) for v in buf[i + 3:i + 3 + k]]
@@ -256,6 +261,8 @@ def plan(n: int, gates: Sequence, log2_tile: int = 12, k_max: int = 2, lookahead
         d = buf[i + 12:i + 12 + ln]
         if t == 3:
             data = (complex(d[0], d[1]), d[2:2 + n].copy(), d[2 + n:2 + 2 * n].copy())
+        elif t == 4:
+            data = [int(v) for v in d]
         else:
             c = d[0::2] + 1j * d[1::2]
             data = c.reshape(1 << k, 1 << k) if t == 0 else c

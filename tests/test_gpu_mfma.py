@@ -212,7 +212,7 @@ def test_host_store_with_matrix_cores_matches_device():
     for store in ("device", "host"):
         log("mfma store", store)
         with _sim(n, "c64", eb=eb, chunk_qubits=14, k_max=4, mma="f32", store=store,
-                  options={"tile_qubits": 12}) as s:
+                  options={"tile_qubits": 12, "relabel_swaps": 0}) as s:
             s.init_basis(x)
             s.apply(gates)
             outs.append(s.amplitudes())

@@ -46,6 +46,13 @@ def _op_matrix(n, op):
     """Full 2^n operator of one exported op."""
     N = 1 << n
     idx = np.arange(N)
+    if op["type"] == "order":
+        new = np.zeros(N, dtype=int)
+        for q, t in enumerate(op["data"]):
+            new |= ((idx >> q) & 1) << t
+        P = np.zeros((N, N), dtype=np.complex128)
+        P[new, idx] = 1.0
+        return P
     if op["type"] == "phase":
         G, mu, lam = op["data"]
         bits = (idx[:, None] >> np.arange(n)[None, :]) & 1
@@ -131,3 +138,69 @@ def test_qft_cascades_become_phase_ops(plan):
     assert kinds.count("phase") >= n - 6
     assert np.max(np.abs(_plan_unitary(8, plan(8, qft(8), log2_tile=6, k_max=2)[1])
                          - brute.circuit_unitary(8, qft(8)))) < 1e-12
+
+
+def _swap_heavy(n, count, seed):
+    """Mixed gates with extra SWAPs, many between qubits >= 6."""
+    rng = np.random.default_rng(seed)
+    g = _mixed(n, count, seed)
+    out = []
+    for gate in g:
+        out.append(gate)
+        if rng.random() < 0.4:
+            a, b = (int(v) for v in rng.choice(np.arange(6, n), 2, replace=False))
+            out.append(Gate("SWAP", a, b))
+    return out
+
+
+@pytest.mark.parametrize("n,tb,k,la", [(8, 6, 2, 64), (9, 7, 2, 1024), (10, 8, 3, 0), (10, 7, 1, 4096),
+                                      (10, 6, 2, 16)])
+def test_relabelled_plan_composes_to_circuit_unitary(plan, n, tb, k, la):
+    """With SWAPs renamed away, the ops (on renamed qubits) followed by the
+    last pass's order record still compose to the circuit's unitary."""
+    gates = _swap_heavy(n, 60, seed=n * 3 + k)
+    n_passes, ops = plan(n, gates, log2_tile=tb, k_max=k, lookahead=la, relabel=True)
+    ref = brute.circuit_unitary(n, gates)
+    assert np.max(np.abs(_plan_unitary(n, ops) - ref)) < 1e-12
+    # qubits 0..5 never move, so the renamed SWAPs are those of two qubits >= 6
+    pos = list(range(n))
+    for g in gates:
+        if g.name == "SWAP" and min(g.q0, g.q1) >= 6:
+            pos[g.q0], pos[g.q1] = pos[g.q1], pos[g.q0]
+    orders = [o for o in ops if o["type"] == "order"]
+    if pos == list(range(n)):
+        assert not orders
+    else:
+        assert len(orders) == 1 and orders[0] is ops[-1] and orders[0]["pass"] == n_passes - 1
+        assert all(orders[0]["data"][pos[q]] == q for q in range(n))
+    for op in ops:
+        if op["type"] == "dense":
+            for q in op["qubits"]:
+                assert (op["tile_mask"] >> q) & 1, "dense op outside its tile"
+
+
+def test_relabel_only_swaps_and_no_swaps(plan):
+    """Only SWAPs: one pass without ops that reorders; no SWAPs of qubits >= 6:
+    the same plan as without relabelling and no order record."""
+    n = 9
+    gates = [Gate("SWAP", 6, 8), Gate("SWAP", 7, 6)]
+    n_passes, ops = plan(n, gates, log2_tile=6, k_max=2, relabel=True)
+    assert n_passes == 1 and [o["type"] for o in ops] == ["order"]
+    assert ops[0]["data"] == [0, 1, 2, 3, 4, 5, 8, 6, 7]
+    assert np.max(np.abs(_plan_unitary(n, ops) - brute.circuit_unitary(n, gates))) < 1e-15
+    gates = _mixed(n, 40, seed=1)
+    gates = [g for g in gates if g.name != "SWAP" or min(g.q0, g.q1) < 6]
+    a = plan(n, gates, log2_tile=7, k_max=2, relabel=True)
+    b = plan(n, gates, log2_tile=7, k_max=2, relabel=False)
+    assert a[0] == b[0] and len(a[1]) == len(b[1])
+    assert all(o["type"] != "order" for o in a[1])
+
+
+def test_relabel_reduces_qft_passes(plan):
+    """The QFT's closing SWAPs pair qubit j with n-1-j; those between qubits
+    >= 6 cost no pass once renamed (28 qubits, tiles of 2^12)."""
+    for seed in (0, 1, 2):
+        _, gates = qft_plus_random(28, 100, seed=seed)
+        with_rl = plan(28, gates, log2_tile=12, k_max=2, relabel=True)[0]
+        without = plan(28, gates, log2_tile=12, k_max=2, relabel=False)[0]
+        assert with_rl < without
