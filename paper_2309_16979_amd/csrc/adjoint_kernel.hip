@@ -44,7 +44,7 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(PassGeom geo, Adjoint
 
     const T *pool = (const T *)buf.psi.pool;
     for (int oi = 0; oi < geo.n_ops; ++oi) {
-        const OpDesc op = buf.psi.ops[geo.op_begin + oi];
+        const OpDesc op = load_op(buf.psi.ops + geo.op_begin + oi);
         const T *M = pool + 2 * (int64_t)op.mat;
         if (op.type == OP_GRAD) {
             double ar = 0.0, ai = 0.0;

@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
+#include "tile_ops.h"
 
 namespace msv {
 
@@ -148,26 +149,27 @@ __device__ __forceinline__ void op_mfma(T *__restrict__ samp, const OpDesc &op, 
 #pragma unroll
         for (int e = 0; e < EPL; ++e) {
             const int rho = KK * t + EPL * q + e;
-            pb[t][e] = (rho < D ? 0 : TILE) + op_offset<K>(pos, rho & (D - 1));
+            pb[t][e] = (rho < D ? 0 : TILE) | swz(op_offset<K>(pos, rho & (D - 1)));
         }
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = 16 * rb + Tr::crow(q, r);
-            pc[rb][r] = (row < D ? 0 : TILE) + op_offset<K>(pos, row & (D - 1));
+            pc[rb][r] = (row < D ? 0 : TILE) | swz(op_offset<K>(pos, row & (D - 1)));
         }
 
     for (int ct = wave; ct < NCT; ct += NW) {
         int l0 = ct * 16 + j;
 #pragma unroll
         for (int m = 0; m < K; ++m) l0 = ((l0 >> sp[m]) << (sp[m] + 1)) | (l0 & ((1 << sp[m]) - 1));
+        l0 = swz(l0);
         Op b[KS];
 #pragma unroll
         for (int t = 0; t < KS; ++t) {
             T v[EPL];
 #pragma unroll
-            for (int e = 0; e < EPL; ++e) v[e] = samp[l0 + pb[t][e]];
+            for (int e = 0; e < EPL; ++e) v[e] = samp[l0 ^ pb[t][e]];
             b[t] = Tr::pack(v);
         }
 #pragma unroll
@@ -176,7 +178,7 @@ __device__ __forceinline__ void op_mfma(T *__restrict__ samp, const OpDesc &op, 
 #pragma unroll
             for (int t = 0; t < KS; ++t) c = Tr::mma(a[rb][t], b[t], c);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) samp[l0 + pc[rb][r]] = (T)c[r];
+            for (int r = 0; r < 4; ++r) samp[l0 ^ pc[rb][r]] = (T)c[r];
         }
     }
 }

@@ -51,7 +51,7 @@ __device__ __forceinline__ void pass_tile(const PassGeom &geo, const PassBuffers
 
     const T *pool = (const T *)buf.pool;
     for (int oi = 0; oi < geo.n_ops; ++oi) {
-        const OpDesc op = buf.ops[geo.op_begin + oi];
+        const OpDesc op = load_op(buf.ops + geo.op_begin + oi);
         if (op.type == OP_SEG) {
             if constexpr (TB >= 10 && TB <= 13)
                 run_segment<T, TB>(samp, op, buf.ops + geo.op_begin + oi + 1, pool, base, tile);

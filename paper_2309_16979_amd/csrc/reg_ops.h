@@ -48,8 +48,9 @@ __device__ __forceinline__ int reg_rank(uint32_t smask, int p)
 // ---------------------------------------------------------------- dense
 
 template <typename T, int R, int RB, bool REAL>
-__device__ __forceinline__ void reg_dense1(T *re, T *im, const T *__restrict__ M)
+__device__ __forceinline__ void reg_dense1(T *re, T *im, const T *__restrict__ Mg)
 {
+    const ConstPtr<T> M = as_const(Mg);
     T mr[4], mi[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -85,8 +86,9 @@ __device__ __forceinline__ void reg_dense1(T *re, T *im, const T *__restrict__ M
 
 // Matrix index s = b(register bit A) + 2 b(register bit B), A < B.
 template <typename T, int R, int A, int B, bool REAL>
-__device__ __forceinline__ void reg_dense2(T *re, T *im, const T *__restrict__ M)
+__device__ __forceinline__ void reg_dense2(T *re, T *im, const T *__restrict__ Mg)
 {
+    const ConstPtr<T> M = as_const(Mg);
     T mr[16], mi[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
@@ -210,8 +212,9 @@ __device__ __forceinline__ void reg_phase(T *re, T *im, const OpDesc &op, uint32
                                           const T *__restrict__ tab, uint64_t base, uint64_t tile)
 {
     constexpr int NR = 1 << R;
-    const T *U0 = tab, *U1 = tab + 2 * NR, *P0 = tab + 4 * NR, *P1 = P0 + 512;
-    const T *TA = P1 + 512, *TAB = TA + 512 * op.k;
+    const ConstPtr<T> U0 = as_const(tab), U1 = as_const(tab + 2 * NR);
+    const T *P0 = tab + 4 * NR, *P1 = P0 + 512;
+    const ConstPtr<T> TA = as_const(P1 + 512), TAB = as_const(P1 + 512 + 512 * op.k);
     const int tid = threadIdx.x;
     T f0r = P0[2 * tid], f0i = P0[2 * tid + 1], f1r = P1[2 * tid], f1i = P1[2 * tid + 1];
     for (int g = 0; g < op.k; ++g) {
@@ -260,15 +263,16 @@ __device__ __forceinline__ void run_segment(T *samp, const OpDesc &seg, const Op
     int tbase = threadIdx.x;
 #pragma unroll
     for (int r = 0; r < R; ++r) tbase = ((tbase >> S[r]) << (S[r] + 1)) | (tbase & ((1 << S[r]) - 1));
+    const int pbase = swz(tbase);
     T re[NR], im[NR];
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
-        const int l = tbase | reg_offset<R>(S, i);
+        const int l = pbase ^ swz(reg_offset<R>(S, i));
         re[i] = samp[l];
         im[i] = samp[TILE + l];
     }
     for (int k = 0; k < seg.k; ++k) {
-        const OpDesc op = sops[k];
+        const OpDesc op = load_op(sops + k);
         const T *M = pool + 2 * (int64_t)op.mat;
         if (op.type == OP_DENSE) {
             if (op.ctrl_fixed == 0 || (base & op.ctrl_fixed) == op.ctrl_fixed) reg_dense<T, R>(re, im, op, smask, M);
@@ -280,7 +284,7 @@ __device__ __forceinline__ void run_segment(T *samp, const OpDesc &seg, const Op
     }
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
-        const int l = tbase | reg_offset<R>(S, i);
+        const int l = pbase ^ swz(reg_offset<R>(S, i));
         samp[l] = re[i];
         samp[TILE + l] = im[i];
     }

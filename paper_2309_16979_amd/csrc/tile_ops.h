@@ -17,6 +17,19 @@ template <typename T> struct Cplx;
 template <> struct Cplx<float> { using V = float2; };
 template <> struct Cplx<double> { using V = double2; };
 
+// Op coefficients (matrices, diagonal tables) are read-only for the whole
+// launch and, per op, the same for every thread: reading them through the
+// constant address space lets the compiler fetch them with scalar loads into
+// SGPRs instead of one vector load per thread into VGPRs.
+template <typename T>
+using ConstPtr = const __attribute__((address_space(4))) T *;
+
+template <typename T>
+__device__ __forceinline__ ConstPtr<T> as_const(const T *p)
+{
+    return (ConstPtr<T>)p;
+}
+
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -27,7 +40,27 @@ __device__ __forceinline__ uint64_t block_index(const BlockStore &s, uint64_t B)
     return ((uint64_t)s.chunk_slot[B >> s.log2_nb] << s.log2_nb) | (B & nbm);
 }
 
+// One op descriptor through the constant address space: the index is the
+// same for every thread, so the words arrive by scalar loads in SGPRs.
+__device__ __forceinline__ OpDesc load_op(const OpDesc *p)
+{
+    static_assert(sizeof(OpDesc) % 4 == 0, "OpDesc is read as 32-bit words");
+    OpDesc o;
+    const ConstPtr<uint32_t> w = as_const(reinterpret_cast<const uint32_t *>(p));
+    uint32_t *d = reinterpret_cast<uint32_t *>(&o);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(OpDesc) / 4); ++i) d[i] = w[i];
+    return o;
+}
+
 // ------------------------------------------------------------- geometry
+
+// LDS position of tile element l within its plane: bits 6.. are XOR-folded
+// onto bits 0..5. The map is its own inverse and linear over XOR, so
+// swz(a | b) = swz(a) ^ swz(b) for disjoint a, b. Accesses whose 64 lanes
+// vary over tile bits above 5 (register segments and dense ops on low
+// qubits) then spread over the LDS banks instead of hitting a few.
+__device__ __forceinline__ int swz(int l) { return l ^ ((l >> 6) & 63); }
 
 // Global index of the tile's amplitude 0: the tile id's bits deposited into
 // the non-tile positions in ascending order.
@@ -81,8 +114,9 @@ __device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, co
             const int jb = wave + NW * i;
             if (jb < NAB) {
                 if (sc != 1.0) { v[i].x *= scale; v[i].y *= scale; }
-                sre[jb * 64 + lane] = v[i].x;
-                sim[jb * 64 + lane] = v[i].y;
+                const int p = swz(jb * 64 + lane);
+                sre[p] = v[i].x;
+                sim[p] = v[i].y;
             }
         }
         return;
@@ -126,8 +160,9 @@ __device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, co
                           __builtin_amdgcn_readlane(av, 2 * a + 1), qr, qi);
             T xr = dequantize<T>(qr, step), xi = dequantize<T>(qi, step);
             if (sc != 1.0) { xr *= scale; xi *= scale; }
-            sre[jb * 64 + lane] = xr;
-            sim[jb * 64 + lane] = xi;
+            const int p = swz(jb * 64 + lane);
+            sre[p] = xr;
+            sim[p] = xi;
         }
     }
 }
@@ -150,8 +185,9 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
         V2 *a = (V2 *)amps;
         for (int jb = wave; jb < NAB; jb += NW) {
             V2 v;
-            v.x = sre[jb * 64 + lane];
-            v.y = sim[jb * 64 + lane];
+            const int p = swz(jb * 64 + lane);
+            v.x = sre[p];
+            v.y = sim[p];
             const double xr = v.x, xi = v.y;
             nrm += xr * xr + xi * xi;
             a[(sG[jb] << 6) | (uint64_t)lane] = v;
@@ -162,7 +198,7 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
     // E1 (per amplitude block, both planes): codes, residuals, widths; the
     // zigzag residuals replace the values in LDS
     for (int jb = wave; jb < NAB; jb += NW) {
-        const int l = jb * 64 + lane;
+        const int l = swz(jb * 64 + lane);
         const T xr = sre[l], xi = sim[l];
         const double dr = (double)xr, di = (double)xi;
         nrm += dr * dr + di * di;
@@ -212,7 +248,7 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
     // E3: bit planes of both planes into this tile's heap slot; then lane j
     // of the wave writes width, anchor and offset of the wave's stream block j
     for (int jb = wave; jb < NAB; jb += NW) {
-        const int l = jb * 64 + lane;
+        const int l = swz(jb * 64 + lane);
         const uint32_t ur = reinterpret_cast<const uint32_t *>(sre)[l * VPT];
         const uint32_t ui = reinterpret_cast<const uint32_t *>(sim)[l * VPT];
         const uint32_t Wr = sW[2 * jb], Wi = sW[2 * jb + 1];
@@ -267,7 +303,7 @@ __device__ __forceinline__ void op_dense(T *__restrict__ sre, T *__restrict__ si
 #pragma unroll
         for (int m = 0; m < K; ++m)
             if ((s >> m) & 1) o |= 1 << op.pos[m];
-        offs[s] = o;
+        offs[s] = swz(o);
     }
     const int cl = (int)op.ctrl_local;
     for (int w = threadIdx.x; w < NG * TPG; w += kThreads) {
@@ -276,9 +312,10 @@ __device__ __forceinline__ void op_dense(T *__restrict__ sre, T *__restrict__ si
 #pragma unroll
         for (int m = 0; m < K; ++m) l0 = ((l0 >> sp[m]) << (sp[m] + 1)) | (l0 & ((1 << sp[m]) - 1));
         if ((l0 & cl) != cl) continue;
+        const int p0 = swz(l0);
         T vr[D], vi[D];
 #pragma unroll
-        for (int s = 0; s < D; ++s) { vr[s] = sre[l0 + offs[s]]; vi[s] = sim[l0 + offs[s]]; }
+        for (int s = 0; s < D; ++s) { vr[s] = sre[p0 ^ offs[s]]; vi[s] = sim[p0 ^ offs[s]]; }
 #pragma unroll
         for (int rr = 0; rr < RPT; ++rr) {
             const int r = rb * RPT + rr;
@@ -300,10 +337,10 @@ __device__ __forceinline__ void op_dense(T *__restrict__ sre, T *__restrict__ si
                     ai = fmaT(mi, vr[s], ai);
                 }
             }
-            int lr = l0;
+            int lr = p0;
 #pragma unroll
             for (int s = 0; s < D; ++s)
-                if (s == r) lr = l0 + offs[s];
+                if (s == r) lr = p0 ^ offs[s];
             sre[lr] = ar;
             sim[lr] = ai;
         }
@@ -341,9 +378,10 @@ __device__ __forceinline__ void op_diag(T *__restrict__ sre, T *__restrict__ sim
     for (int l = threadIdx.x; l < (1 << TB); l += kThreads) {
         const int s = diag_index<K>(op, fixed_s, l);
         const T dr = dv[2 * s], di = dv[2 * s + 1];
-        const T xr = sre[l], xi = sim[l];
-        sre[l] = fmaT(xr, dr, -xi * di);
-        sim[l] = fmaT(xr, di, xi * dr);
+        const int p = swz(l);
+        const T xr = sre[p], xi = sim[p];
+        sre[p] = fmaT(xr, dr, -xi * di);
+        sim[p] = fmaT(xr, di, xi * dr);
     }
 }
 
@@ -406,9 +444,10 @@ __device__ __forceinline__ void op_phase(T *__restrict__ sre, T *__restrict__ si
         const T fr = lo[2 * a], fi = lo[2 * a + 1];
         const T gr = hi[2 * h], gi = hi[2 * h + 1];
         const T pr = fr * gr - fi * gi, pi = fr * gi + fi * gr;
-        const T xr = sre[l], xi = sim[l];
-        sre[l] = fmaT(xr, pr, -xi * pi);
-        sim[l] = fmaT(xr, pi, xi * pr);
+        const int p = swz(l);
+        const T xr = sre[p], xi = sim[p];
+        sre[p] = fmaT(xr, pr, -xi * pi);
+        sim[p] = fmaT(xr, pi, xi * pr);
     }
 }
 
@@ -425,8 +464,9 @@ __device__ __forceinline__ void op_obs(T *__restrict__ sre, T *__restrict__ sim,
         const uint64_t g = (sG[l >> 6] << 6) | (uint64_t)(l & 63);
         double v = 0.0;
         for (int t = 0; t < n_terms; ++t) v += (__popcll(g & masks[t]) & 1) ? -coeffs[t] : coeffs[t];
-        sre[l] = (T)(sre[l] * v);
-        sim[l] = (T)(sim[l] * v);
+        const int p = swz(l);
+        sre[p] = (T)(sre[p] * v);
+        sim[p] = (T)(sim[p] * v);
     }
 }
 
@@ -488,15 +528,16 @@ __device__ __forceinline__ void probe_dense(const T *pre, const T *pim, const T 
 #pragma unroll
         for (int m = 0; m < K; ++m)
             if ((s >> m) & 1) o |= 1 << op.pos[m];
-        offs[s] = o;
+        offs[s] = swz(o);
     }
     for (int g = threadIdx.x; g < NG; g += kThreads) {
         int l0 = g;
 #pragma unroll
         for (int m = 0; m < K; ++m) l0 = ((l0 >> sp[m]) << (sp[m] + 1)) | (l0 & ((1 << sp[m]) - 1));
+        const int p0 = swz(l0);
         double vr[D], vi[D];
 #pragma unroll
-        for (int s = 0; s < D; ++s) { vr[s] = pre[l0 + offs[s]]; vi[s] = pim[l0 + offs[s]]; }
+        for (int s = 0; s < D; ++s) { vr[s] = pre[p0 ^ offs[s]]; vi[s] = pim[p0 ^ offs[s]]; }
 #pragma unroll
         for (int r = 0; r < D; ++r) {
             double ar = 0.0, ai = 0.0;
@@ -506,7 +547,7 @@ __device__ __forceinline__ void probe_dense(const T *pre, const T *pim, const T 
                 ar += mr * vr[s] - mi * vi[s];
                 ai += mr * vi[s] + mi * vr[s];
             }
-            const double yr = lre[l0 + offs[r]], yi = lim[l0 + offs[r]];
+            const double yr = lre[p0 ^ offs[r]], yi = lim[p0 ^ offs[r]];
             accr += yr * ar + yi * ai;   // conj(lambda) * (A psi)
             acci += yr * ai - yi * ar;
         }
@@ -521,9 +562,10 @@ __device__ __forceinline__ void probe_diag(const T *pre, const T *pim, const T *
     for (int l = threadIdx.x; l < (1 << TB); l += kThreads) {
         const int s = diag_index<K>(op, fixed_s, l);
         const double dr = dv[2 * s], di = dv[2 * s + 1];
-        const double xr = pre[l], xi = pim[l];
+        const int p = swz(l);
+        const double xr = pre[p], xi = pim[p];
         const double ar = dr * xr - di * xi, ai = dr * xi + di * xr;
-        const double yr = lre[l], yi = lim[l];
+        const double yr = lre[p], yi = lim[p];
         accr += yr * ar + yi * ai;
         acci += yr * ai - yi * ar;
     }
