@@ -199,6 +199,51 @@ __device__ __forceinline__ void reg_diag(T *re, T *im, const OpDesc &op, uint32_
 
 // ------------------------------------------------------ controlled phase
 
+// RC: register bit of the control (0 <= RC < R, so every element knows its
+// control statically), or -1 when the control is a thread bit, a bit of the
+// tile's base, or absent (then `on_t` holds it per thread).
+template <typename T, int R, int RC>
+__device__ __forceinline__ void reg_phase_apply(T *re, T *im, T f0r, T f0i, T f1r, T f1i, bool on_t,
+                                                const ConstPtr<T> U0, const ConstPtr<T> U1)
+{
+    constexpr int NR = 1 << R;
+    if (RC < 0) {
+        // one thread factor for all of the thread's elements
+        const T fr = on_t ? f1r : f0r, fi = on_t ? f1i : f0i;
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const T u0r = U0[2 * i], u0i = U0[2 * i + 1], u1r = U1[2 * i], u1i = U1[2 * i + 1];
+            const T ur = on_t ? u1r : u0r, ui = on_t ? u1i : u0i;
+            const T pr = fr * ur - fi * ui, pi = fr * ui + fi * ur;
+            const T xr = re[i], xi = im[i];
+            re[i] = fmaT(xr, pr, -xi * pi);
+            im[i] = fmaT(xr, pi, xi * pr);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            const bool on = ((i >> RC) & 1) != 0;
+            const T fr = on ? f1r : f0r, fi = on ? f1i : f0i;
+            const T ur = on ? U1[2 * i] : U0[2 * i], ui = on ? U1[2 * i + 1] : U0[2 * i + 1];
+            const T pr = fr * ur - fi * ui, pi = fr * ui + fi * ur;
+            const T xr = re[i], xi = im[i];
+            re[i] = fmaT(xr, pr, -xi * pi);
+            im[i] = fmaT(xr, pi, xi * pr);
+        }
+    }
+    variant_end<2000 + RC>();
+}
+
+template <typename T, int R, int RC = -1>
+__device__ __forceinline__ void reg_phase_at(int rc, T *re, T *im, T f0r, T f0i, T f1r, T f1i, bool on_t,
+                                             const ConstPtr<T> U0, const ConstPtr<T> U1)
+{
+    if constexpr (RC < R) {
+        if (rc == RC) reg_phase_apply<T, R, RC>(re, im, f0r, f0i, f1r, f1i, on_t, U0, U1);
+        else reg_phase_at<T, R, RC + 1>(rc, re, im, f0r, f0i, f1r, f1i, on_t, U0, U1);
+    }
+}
+
 // factor(l) = A(l) (b_c(l) ? B(l) : 1) with A, B products of per-qubit phases
 // (and a global factor in A), split as F(thread bits, tile bits outside the
 // tile) * U(register index). Pool layout (complex entries): U0[2^R], U1[2^R]
@@ -231,19 +276,10 @@ __device__ __forceinline__ void reg_phase(T *re, T *im, const OpDesc &op, uint32
     const int cp = op.ctrl_pos;
     const bool has_ctrl = op.ctrl_q >= 0;
     const bool ctrl_reg = has_ctrl && cp >= 0 && ((smask >> cp) & 1u);
-    const int rc = ctrl_reg ? reg_rank(smask, cp) : 0;
     bool on_t = false;   // control from the thread's bits or the tile base
     if (has_ctrl && !ctrl_reg) on_t = cp >= 0 ? ((tbase >> cp) & 1) != 0 : ((base >> op.ctrl_q) & 1ull) != 0;
-#pragma unroll
-    for (int i = 0; i < NR; ++i) {
-        const bool on = ctrl_reg ? ((i >> rc) & 1) != 0 : on_t;
-        const T fr = on ? f1r : f0r, fi = on ? f1i : f0i;
-        const T ur = on ? U1[2 * i] : U0[2 * i], ui = on ? U1[2 * i + 1] : U0[2 * i + 1];
-        const T pr = fr * ur - fi * ui, pi = fr * ui + fi * ur;
-        const T xr = re[i], xi = im[i];
-        re[i] = fmaT(xr, pr, -xi * pi);
-        im[i] = fmaT(xr, pi, xi * pr);
-    }
+    if (ctrl_reg) reg_phase_at<T, R, 0>(reg_rank(smask, cp), re, im, f0r, f0i, f1r, f1i, false, U0, U1);
+    else reg_phase_apply<T, R, -1>(re, im, f0r, f0i, f1r, f1i, on_t, U0, U1);
 }
 
 // ---------------------------------------------------------------- segment
