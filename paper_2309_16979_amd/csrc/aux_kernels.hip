@@ -126,15 +126,19 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, Bloc
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     // Z-strings: the sign of term t at index i = (G << 6) | lane factors into a
     // lane part, folded into tl[t] = c_t (-1)^popcount(lane & m_t) once, and a
-    // block part applied per block.
+    // block part (-1)^popcount(G & (m_t >> 6)), the same for the whole block:
+    // lane t evaluates it for term t and one ballot hands every block sign to
+    // the wave as a scalar bit mask.
     const bool fast = a.kind == RED_EXPZ && a.n_terms <= kFastTerms;
     double tl[kFastTerms];
+    uint64_t mhi = 0;
     if (fast) {
 #pragma unroll
         for (int t = 0; t < kFastTerms; ++t)
             tl[t] = t < a.n_terms ? ((__popc((uint32_t)(a.masks[t] & 63u) & (uint32_t)lane) & 1) ? -a.coeffs[t]
                                                                                                  : a.coeffs[t])
                                   : 0.0;
+        if (lane < a.n_terms) mhi = a.masks[lane] >> 6;
     }
     for_amp_blocks<T, COMP>(amps, st, step, first, nab, wave, lane, [&](uint64_t G, double xr, double xi) {
         xr *= a.scale;
@@ -147,10 +151,11 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, Bloc
         } else if (a.kind == RED_EXPZ) {
             double v = 0.0;
             if (fast) {
+                const uint64_t neg = __ballot((__popcll(G & mhi) & 1) != 0);
 #pragma unroll
                 for (int t = 0; t < kFastTerms; ++t) {
                     if (t >= a.n_terms) break;
-                    const double sg = (__popcll((G << 6) & a.masks[t]) & 1) ? -1.0 : 1.0;
+                    const double sg = ((neg >> t) & 1ull) ? -1.0 : 1.0;
                     v = __builtin_fma(sg, tl[t], v);
                 }
             } else {
