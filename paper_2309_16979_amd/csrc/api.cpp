@@ -268,23 +268,24 @@ int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOpt
         }
         s->stats.pass_bytes = bytes;
         // algorithmic work: gate arithmetic per amplitude and codec work per value
-        double valu = 0.0, mflops = 0.0;
+        double gate = 0.0, codec = 0.0, mflops = 0.0;
         const double amps = std::ldexp(1.0, s->n), vals = 2.0 * amps;
         words_in = (double)s->compressed_words;
         for (size_t p = 0; p < n_passes; ++p) {
             for (int i = geoms[p].op_begin; i < geoms[p].op_begin + geoms[p].n_ops; ++i) {
                 const OpDesc &d = ops[i];
-                if (d.type == OP_DENSE) valu += amps * (d.real ? 2.0 : 4.0) * (double)(1 << d.k);
-                else if (d.type == OP_DIAG) valu += amps * 4.0;
-                else if (d.type == OP_PHASE || d.type == OP_RPHASE) valu += amps * 8.0;
+                if (d.type == OP_DENSE) gate += amps * (d.real ? 2.0 : 4.0) * (double)(1 << d.k);
+                else if (d.type == OP_DIAG) gate += amps * 4.0;
+                else if (d.type == OP_PHASE || d.type == OP_RPHASE) gate += amps * 8.0;
                 else if (d.type == OP_MFMA) mflops += amps * 8.0 * (double)(1 << d.k);
             }
             if (s->compressed()) {
-                valu += 64.0 * (words_in + hout[3 * p + 2]) + 2.0 * 15.0 * vals;
+                codec += 64.0 * (words_in + hout[3 * p + 2]) + 2.0 * 15.0 * vals;
                 words_in = hout[3 * p + 2];
             }
         }
-        s->stats.pass_valu_ops = valu;
+        s->stats.pass_valu_ops = gate + codec;
+        s->stats.pass_issue_ops = (s->is_double() ? 1.0 : 0.5) * gate + codec;
         s->stats.pass_mfma_flops = mflops;
     }
     if (n_passes) {

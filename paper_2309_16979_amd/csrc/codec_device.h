@@ -73,7 +73,7 @@ __device__ __forceinline__ T dequantize(int32_t q, double step)
 __device__ __forceinline__ uint32_t residual_zigzag(int32_t q)
 {
     uint32_t prev = wave_shift_up1((uint32_t)q);
-    asm volatile("" : "+v"(prev));
+    asm("" : "+v"(prev));
     const int32_t d = lane_id() == 0 ? 0 : (int32_t)((uint32_t)q - prev);
     return ((uint32_t)d << 1) ^ (uint32_t)(d >> 31);
 }
@@ -160,6 +160,82 @@ __device__ __forceinline__ void unpack_codes2(uint64_t mr, uint32_t Wr, int32_t 
     if (Wm) wave_inclusive_sum2(dr, di);
     qr = (int32_t)((uint32_t)Ar + dr);
     qi = (int32_t)((uint32_t)Ai + di);
+}
+
+// Four independent inclusive prefix sums, interleaved.
+__device__ __forceinline__ void wave_inclusive_sum4(uint32_t *x)
+{
+#define MSV_SCAN_STEP(C, R, B, Z)                                              \
+    _Pragma("unroll") for (int p = 0; p < 4; ++p) x[p] += dpp_u32<C, R, B, Z>(x[p]);
+    MSV_SCAN_STEP(0x111, 0xf, 0xf, true)
+    MSV_SCAN_STEP(0x112, 0xf, 0xf, true)
+    MSV_SCAN_STEP(0x114, 0xf, 0xf, true)
+    MSV_SCAN_STEP(0x118, 0xf, 0xf, true)
+    MSV_SCAN_STEP(0x142, 0xa, 0xf, false)
+    MSV_SCAN_STEP(0x143, 0xc, 0xf, false)
+#undef MSV_SCAN_STEP
+}
+
+// Widths of four blocks (OR reductions interleaved).
+__device__ __forceinline__ void block_width4(const uint32_t *u_in, uint32_t *w)
+{
+    uint32_t u[4] = {u_in[0], u_in[1], u_in[2], u_in[3]};
+#define MSV_OR_STEP(C, R, B, Z)                                                \
+    _Pragma("unroll") for (int p = 0; p < 4; ++p) u[p] |= dpp_u32<C, R, B, Z>(u[p]);
+    MSV_OR_STEP(0x111, 0xf, 0xf, true)
+    MSV_OR_STEP(0x112, 0xf, 0xf, true)
+    MSV_OR_STEP(0x114, 0xf, 0xf, true)
+    MSV_OR_STEP(0x118, 0xf, 0xf, true)
+    MSV_OR_STEP(0x142, 0xa, 0xf, false)
+    MSV_OR_STEP(0x143, 0xc, 0xf, false)
+#undef MSV_OR_STEP
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)u[p], 63);
+        w[p] = o ? 32u - (uint32_t)__builtin_clz(o) : 0u;
+    }
+}
+
+// Codes of four blocks (two amplitude blocks, both planes each). Lane k holds
+// word k of block p in m[p] and 0 for k at or beyond its width, so all four
+// unpack in one loop up to the largest width.
+__device__ __forceinline__ void unpack_codes4(const uint64_t *m, const uint32_t *W, const int32_t *A, int32_t *q)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t sh = lane & 31u;
+    const bool hi = lane >= 32u;
+    const uint32_t Wm = max(max(W[0], W[1]), max(W[2], W[3]));
+    uint32_t u[4] = {0u, 0u, 0u, 0u};
+    for (uint32_t k = 0; k < Wm; ++k) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const uint32_t w_lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)m[p], (int)k);
+            const uint32_t w_hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(m[p] >> 32), (int)k);
+            u[p] |= (((hi ? w_hi : w_lo) >> sh) & 1u) << k;
+        }
+    }
+    uint32_t d[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) d[p] = (u[p] >> 1) ^ (0u - (u[p] & 1u));
+    if (Wm) wave_inclusive_sum4(d);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) q[p] = (int32_t)((uint32_t)A[p] + d[p]);
+}
+
+// Lane k (< W[p]) receives bit-plane word k of block p, for four blocks.
+__device__ __forceinline__ void pack_planes4(const uint32_t *u, const uint32_t *W, uint64_t *mine)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t Wm = max(max(W[0], W[1]), max(W[2], W[3]));
+#pragma unroll
+    for (int p = 0; p < 4; ++p) mine[p] = 0;
+    for (uint32_t k = 0; k < Wm; ++k) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const uint64_t bal = __builtin_amdgcn_ballot_w64(((u[p] >> k) & 1u) != 0u);
+            if (lane == k) mine[p] = bal;
+        }
+    }
 }
 
 // FP64 sum over the 64 lanes, returned to every lane (butterfly: the same

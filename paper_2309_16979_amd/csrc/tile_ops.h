@@ -149,20 +149,44 @@ __device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, co
             mine[j] = 0;
             if ((uint32_t)lane < W) mine[j] = in.heap[(uint64_t)off + lane];
         }
+        if constexpr (RA % 2 == 0 && APW % RA == 0 && NAB % NW == 0) {
+            // two amplitude blocks (four stream blocks) per unpack loop
 #pragma unroll
-        for (int a = 0; a < RA; ++a) {
-            const int jb = wave + NW * (r0 + a);
-            if (r0 + a >= APW || jb >= NAB) break;
-            int32_t qr, qi;
-            unpack_codes2(mine[2 * a], (uint32_t)__builtin_amdgcn_readlane((int)wv, 2 * a),
-                          __builtin_amdgcn_readlane(av, 2 * a), mine[2 * a + 1],
-                          (uint32_t)__builtin_amdgcn_readlane((int)wv, 2 * a + 1),
-                          __builtin_amdgcn_readlane(av, 2 * a + 1), qr, qi);
-            T xr = dequantize<T>(qr, step), xi = dequantize<T>(qi, step);
-            if (sc != 1.0) { xr *= scale; xi *= scale; }
-            const int p = swz(jb * 64 + lane);
-            sre[p] = xr;
-            sim[p] = xi;
+            for (int a = 0; a < RA; a += 2) {
+                const int jb = wave + NW * (r0 + a);
+                uint32_t W4[4];
+                int32_t A4[4], q4[4];
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                    W4[p] = (uint32_t)__builtin_amdgcn_readlane((int)wv, 2 * a + p);
+                    A4[p] = __builtin_amdgcn_readlane(av, 2 * a + p);
+                }
+                unpack_codes4(mine + 2 * a, W4, A4, q4);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    T xr = dequantize<T>(q4[2 * h], step), xi = dequantize<T>(q4[2 * h + 1], step);
+                    if (sc != 1.0) { xr *= scale; xi *= scale; }
+                    const int p = swz((jb + NW * h) * 64 + lane);
+                    sre[p] = xr;
+                    sim[p] = xi;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < RA; ++a) {
+                const int jb = wave + NW * (r0 + a);
+                if (r0 + a >= APW || jb >= NAB) break;
+                int32_t qr, qi;
+                unpack_codes2(mine[2 * a], (uint32_t)__builtin_amdgcn_readlane((int)wv, 2 * a),
+                              __builtin_amdgcn_readlane(av, 2 * a), mine[2 * a + 1],
+                              (uint32_t)__builtin_amdgcn_readlane((int)wv, 2 * a + 1),
+                              __builtin_amdgcn_readlane(av, 2 * a + 1), qr, qi);
+                T xr = dequantize<T>(qr, step), xi = dequantize<T>(qi, step);
+                if (sc != 1.0) { xr *= scale; xi *= scale; }
+                const int p = swz(jb * 64 + lane);
+                sre[p] = xr;
+                sim[p] = xi;
+            }
         }
     }
 }
@@ -196,8 +220,49 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
     }
     bool bad = false;
     // E1 (per amplitude block, both planes): codes, residuals, widths; the
-    // zigzag residuals replace the values in LDS
-    for (int jb = wave; jb < NAB; jb += NW) {
+    // zigzag residuals replace the values in LDS. Two amplitude blocks per
+    // iteration when the wave has an even number of them (independent
+    // chains for the scheduler; sums keep the one-block order).
+    constexpr bool E1_PAIR = NAB % (2 * NW) == 0;
+    if constexpr (E1_PAIR) for (int jb = wave; jb < NAB; jb += 2 * NW) {
+        const int jc = jb + NW;
+        const int l0 = swz(jb * 64 + lane), l1 = swz(jc * 64 + lane);
+        const T x[4] = {sre[l0], sim[l0], sre[l1], sim[l1]};
+        double d[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) d[p] = (double)x[p];
+        nrm += d[0] * d[0] + d[1] * d[1];
+        nrm += d[2] * d[2] + d[3] * d[3];
+        int32_t q[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) q[p] = quantize<T>(x[p], inv_step, bad);
+        if (check) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const T yr = dequantize<T>(q[2 * h], step), yi = dequantize<T>(q[2 * h + 1], step);
+                err = fmax(err, fmax(__builtin_fabs(d[2 * h] - (double)yr), __builtin_fabs(d[2 * h + 1] - (double)yi)));
+            }
+        }
+        uint32_t u[4], W4[4];
+        int32_t A4[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) u[p] = residual_zigzag(q[p]);
+        block_width4(u, W4);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) A4[p] = __builtin_amdgcn_readlane(q[p], 0);
+        reinterpret_cast<uint32_t *>(sre)[l0 * VPT] = u[0];
+        reinterpret_cast<uint32_t *>(sim)[l0 * VPT] = u[1];
+        reinterpret_cast<uint32_t *>(sre)[l1 * VPT] = u[2];
+        reinterpret_cast<uint32_t *>(sim)[l1 * VPT] = u[3];
+        if (lane == 0) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                sW[2 * jb + (p & 1) + 2 * NW * (p >> 1)] = W4[p];
+                sA[2 * jb + (p & 1) + 2 * NW * (p >> 1)] = A4[p];
+            }
+        }
+    }
+    if constexpr (!E1_PAIR) for (int jb = wave; jb < NAB; jb += NW) {
         const int l = swz(jb * 64 + lane);
         const T xr = sre[l], xi = sim[l];
         const double dr = (double)xr, di = (double)xi;
@@ -247,15 +312,33 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
     __syncthreads();
     // E3: bit planes of both planes into this tile's heap slot; then lane j
     // of the wave writes width, anchor and offset of the wave's stream block j
-    for (int jb = wave; jb < NAB; jb += NW) {
-        const int l = swz(jb * 64 + lane);
-        const uint32_t ur = reinterpret_cast<const uint32_t *>(sre)[l * VPT];
-        const uint32_t ui = reinterpret_cast<const uint32_t *>(sim)[l * VPT];
-        const uint32_t Wr = sW[2 * jb], Wi = sW[2 * jb + 1];
-        const uint64_t mr = pack_planes(ur, Wr);
-        const uint64_t mi = pack_planes(ui, Wi);
-        if ((uint32_t)lane < Wr) out.heap[slot + sOff[2 * jb] + lane] = mr;
-        if ((uint32_t)lane < Wi) out.heap[slot + sOff[2 * jb + 1] + lane] = mi;
+    if constexpr (NAB % (2 * NW) == 0) {
+        for (int jb = wave; jb < NAB; jb += 2 * NW) {
+            const int jc = jb + NW;
+            const int l0 = swz(jb * 64 + lane), l1 = swz(jc * 64 + lane);
+            const uint32_t u[4] = {reinterpret_cast<const uint32_t *>(sre)[l0 * VPT],
+                                   reinterpret_cast<const uint32_t *>(sim)[l0 * VPT],
+                                   reinterpret_cast<const uint32_t *>(sre)[l1 * VPT],
+                                   reinterpret_cast<const uint32_t *>(sim)[l1 * VPT]};
+            const uint32_t W4[4] = {sW[2 * jb], sW[2 * jb + 1], sW[2 * jc], sW[2 * jc + 1]};
+            uint64_t m[4];
+            pack_planes4(u, W4, m);
+            const uint32_t o4[4] = {sOff[2 * jb], sOff[2 * jb + 1], sOff[2 * jc], sOff[2 * jc + 1]};
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+                if ((uint32_t)lane < W4[p]) out.heap[slot + o4[p] + lane] = m[p];
+        }
+    } else {
+        for (int jb = wave; jb < NAB; jb += NW) {
+            const int l = swz(jb * 64 + lane);
+            const uint32_t ur = reinterpret_cast<const uint32_t *>(sre)[l * VPT];
+            const uint32_t ui = reinterpret_cast<const uint32_t *>(sim)[l * VPT];
+            const uint32_t Wr = sW[2 * jb], Wi = sW[2 * jb + 1];
+            const uint64_t mr = pack_planes(ur, Wr);
+            const uint64_t mi = pack_planes(ui, Wi);
+            if ((uint32_t)lane < Wr) out.heap[slot + sOff[2 * jb] + lane] = mr;
+            if ((uint32_t)lane < Wi) out.heap[slot + sOff[2 * jb + 1] + lane] = mi;
+        }
     }
     constexpr int APW = (NAB + NW - 1) / NW;
     for (int j0 = 0; j0 < 2 * APW; j0 += 64) {
