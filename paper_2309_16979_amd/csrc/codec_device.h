@@ -142,18 +142,19 @@ __device__ __forceinline__ void block_width2(uint32_t u, uint32_t v, uint32_t &w
 __device__ __forceinline__ void unpack_codes2(uint64_t mr, uint32_t Wr, int32_t Ar, uint64_t mi, uint32_t Wi,
                                               int32_t Ai, int32_t &qr, int32_t &qi)
 {
-    const uint32_t lane = lane_id();
-    const uint32_t sh = lane & 31u;
-    const bool hi = lane >= 32u;
+    // planes from the most significant down, as in unpack_codes4
+    const uint32_t up = 63u - lane_id();
     const uint32_t Wm = Wr > Wi ? Wr : Wi;
     uint32_t ur = 0, ui = 0;
-    for (uint32_t k = 0; k < Wm; ++k) {
+    for (uint32_t k = Wm; k-- > 0;) {
         const uint32_t r_lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mr, (int)k);
         const uint32_t r_hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mr >> 32), (int)k);
         const uint32_t i_lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mi, (int)k);
         const uint32_t i_hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mi >> 32), (int)k);
-        ur |= (((hi ? r_hi : r_lo) >> sh) & 1u) << k;
-        ui |= (((hi ? i_hi : i_lo) >> sh) & 1u) << k;
+        const uint64_t tr = (((uint64_t)r_hi << 32) | r_lo) << up;
+        const uint64_t ti = (((uint64_t)i_hi << 32) | i_lo) << up;
+        ur = __builtin_amdgcn_alignbit(ur, (uint32_t)(tr >> 32), 31u);
+        ui = __builtin_amdgcn_alignbit(ui, (uint32_t)(ti >> 32), 31u);
     }
     uint32_t dr = (ur >> 1) ^ (0u - (ur & 1u));
     uint32_t di = (ui >> 1) ^ (0u - (ui & 1u));
@@ -201,17 +202,18 @@ __device__ __forceinline__ void block_width4(const uint32_t *u_in, uint32_t *w)
 // unpack in one loop up to the largest width.
 __device__ __forceinline__ void unpack_codes4(const uint64_t *m, const uint32_t *W, const int32_t *A, int32_t *q)
 {
-    const uint32_t lane = lane_id();
-    const uint32_t sh = lane & 31u;
-    const bool hi = lane >= 32u;
+    // Planes from the most significant down: word << (63 - lane) puts this
+    // lane's bit on top, and a funnel shift appends it to u.
+    const uint32_t up = 63u - lane_id();
     const uint32_t Wm = max(max(W[0], W[1]), max(W[2], W[3]));
     uint32_t u[4] = {0u, 0u, 0u, 0u};
-    for (uint32_t k = 0; k < Wm; ++k) {
+    for (uint32_t k = Wm; k-- > 0;) {
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             const uint32_t w_lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)m[p], (int)k);
             const uint32_t w_hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(m[p] >> 32), (int)k);
-            u[p] |= (((hi ? w_hi : w_lo) >> sh) & 1u) << k;
+            const uint64_t t = (((uint64_t)w_hi << 32) | w_lo) << up;
+            u[p] = __builtin_amdgcn_alignbit(u[p], (uint32_t)(t >> 32), 31u);
         }
     }
     uint32_t d[4];
