@@ -98,16 +98,23 @@ static __device__ __forceinline__ void for_amp_blocks(const void *amps, const Bl
             mine[j] = 0;
             if ((uint32_t)lane < W) mine[j] = st.heap[(uint64_t)off + lane];
         }
+        // two amplitude blocks per unpack loop; a block beyond the range has
+        // width 0 and anchor 0 and is not handed to f
 #pragma unroll
-        for (int a = 0; a < RA; ++a) {
+        for (int a = 0; a < RA; a += 2) {
             const uint64_t k = k0 + stride * a;
             if (k >= nab) break;
-            int32_t qr, qi;
-            unpack_codes2(mine[2 * a], (uint32_t)__builtin_amdgcn_readlane((int)wv, 2 * a),
-                          __builtin_amdgcn_readlane(av, 2 * a), mine[2 * a + 1],
-                          (uint32_t)__builtin_amdgcn_readlane((int)wv, 2 * a + 1),
-                          __builtin_amdgcn_readlane(av, 2 * a + 1), qr, qi);
-            f(first + k, (double)dequantize<T>(qr, step), (double)dequantize<T>(qi, step));
+            uint32_t W4[4];
+            int32_t A4[4], q4[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                W4[p] = (uint32_t)__builtin_amdgcn_readlane((int)wv, 2 * a + p);
+                A4[p] = __builtin_amdgcn_readlane(av, 2 * a + p);
+            }
+            unpack_codes4(mine + 2 * a, W4, A4, q4);
+            f(first + k, (double)dequantize<T>(q4[0], step), (double)dequantize<T>(q4[1], step));
+            if (k + stride < nab)
+                f(first + k + stride, (double)dequantize<T>(q4[2], step), (double)dequantize<T>(q4[3], step));
         }
     }
 }
@@ -151,10 +158,11 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, Bloc
         } else if (a.kind == RED_EXPZ) {
             double v = 0.0;
             if (fast) {
+                // all kFastTerms slots (tl is 0 beyond n_terms): no branch per
+                // term, one scalar bit test and select per sign
                 const uint64_t neg = __ballot((__popcll(G & mhi) & 1) != 0);
 #pragma unroll
                 for (int t = 0; t < kFastTerms; ++t) {
-                    if (t >= a.n_terms) break;
                     const double sg = ((neg >> t) & 1ull) ? -1.0 : 1.0;
                     v = __builtin_fma(sg, tl[t], v);
                 }
