@@ -172,6 +172,11 @@ int msv_set_fusion(msv_sim *sim, int k_max, int mma_precision);
  *                  permutes 64-amplitude blocks); the last pass of the call
  *                  writes its blocks back in the identity order. 0 = every
  *                  SWAP runs as a 4x4 gate
+ *   "plan_cache"   1 (default) = device store: keep the last call's passes and
+ *                  lowered ops, and reuse them when msv_apply gets the same
+ *                  gates (compared exactly, matrices included) under the same
+ *                  options; the plan is the offline stage of the method.
+ *                  0 = plan every call
  *   "autotune"     1 = choose fusion width and tile size per msv_apply from a
  *                  cost model calibrated once per process on the GPU */
 int msv_set_option(msv_sim *sim, const char *key, double value);

@@ -154,23 +154,31 @@ int alloc_device_store(msv_sim *s)
 }
 
 // Runs a list of passes over the device-resident state (plain or compressed).
+void lower_for(const msv_sim *s, const std::vector<Pass> &passes, const PlanOptions &o, Lowered &low)
+{
+    low.ops.clear();
+    low.poolf.clear();
+    low.poold.clear();
+    low.geoms.clear();
+    if (s->is_double()) low.ok = lower_passes<double>(passes, o, low.ops, low.poold, low.geoms);
+    else low.ok = lower_passes<float>(passes, o, low.ops, low.poolf, low.geoms);
+}
+
 int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOptions &o, double *norm_last,
-                      double *err_last, double *words_last, std::vector<double> *per_pass)
+                      double *err_last, double *words_last, std::vector<double> *per_pass, const Lowered *pre)
 {
     hipStream_t stream = s->stream();
-    std::vector<OpDesc> ops;
-    std::vector<PassGeom> geoms;
-    std::vector<float> poolf;
-    std::vector<double> poold;
-    size_t pool_bytes;
-    bool ok;
-    if (s->is_double()) {
-        ok = lower_passes<double>(passes, o, ops, poold, geoms);
-        pool_bytes = poold.size() * sizeof(double);
-    } else {
-        ok = lower_passes<float>(passes, o, ops, poolf, geoms);
-        pool_bytes = poolf.size() * sizeof(float);
+    Lowered own;
+    if (!pre) {
+        lower_for(s, passes, o, own);
+        pre = &own;
     }
+    const std::vector<OpDesc> &ops = pre->ops;
+    const std::vector<PassGeom> &geoms = pre->geoms;
+    const std::vector<float> &poolf = pre->poolf;
+    const std::vector<double> &poold = pre->poold;
+    const bool ok = pre->ok;
+    const size_t pool_bytes = s->is_double() ? poold.size() * sizeof(double) : poolf.size() * sizeof(float);
     s->stats.mfma_ops = 0;
     for (const OpDesc &d : ops) s->stats.mfma_ops += d.type == OP_MFMA;
     if (!ok) return fail(s, MSV_E_ARG, "internal planner error: op outside its tile");
@@ -440,6 +448,9 @@ int msv_set_option(msv_sim *s, const char *key, double v)
         s->segments = v != 0.0;
     } else if (!strcmp(key, "relabel_swaps")) {
         s->relabel = v != 0.0;
+    } else if (!strcmp(key, "plan_cache")) {
+        s->plan_cache = v != 0.0;
+        s->plan_key.clear();
     } else if (!strcmp(key, "autotune")) {
         s->autotune = v != 0.0;
     } else if (!strcmp(key, "time_passes")) {
@@ -614,23 +625,52 @@ int msv_apply(msv_sim *s, const msv_gate *gates, size_t n_gates)
         o.mma = mma_mode(s);
         o.segments = s->segments;
         o.lookahead = s->lookahead;
-        std::vector<Pass> passes;
         // compressed states live in two stores (ping-pong), so a pass may
         // write its blocks to other positions than it read them from
-        std::vector<int> pos;
-        std::vector<Prim> renamed;
         const bool relabel = s->relabel && s->compressed();
-        if (relabel) renamed = relabel_swaps(prims, s->n, pos);
-        const std::vector<Prim> &pl = relabel ? renamed : prims;
-        if (s->autotune && s->compressed()) {
-            int k = o.k_max, tb = o.tb;
-            if ((st = autotune(s->is_double(), s->stream(), pl, s->n, &k, &tb, &passes))) return st;
-            o.k_max = s->tuned_k = k;
-            o.tb = s->tuned_tb = tb;
-        } else {
-            passes = plan_passes(pl, o);
+        const bool tune = s->autotune && s->compressed();
+        // the offline stage depends only on the gates and these options
+        std::vector<uint64_t> key = {(uint64_t)s->n, (uint64_t)s->dtype, (uint64_t)o.tb, (uint64_t)o.k_max,
+                                     (uint64_t)o.mfma_min_k, (uint64_t)o.mma, (uint64_t)o.segments,
+                                     (uint64_t)o.lookahead, (uint64_t)relabel, (uint64_t)tune, n_gates};
+        for (size_t i = 0; i < n_gates; ++i) {
+            const msv_gate &g = gates[i];
+            uint64_t th;
+            memcpy(&th, &g.theta, 8);
+            key.push_back((uint64_t)g.kind | ((uint64_t)(uint32_t)g.q0 << 32));
+            key.push_back((uint64_t)(uint32_t)g.q1 | ((uint64_t)(uint32_t)g.param << 32));
+            key.push_back(th);
+            const int nm = g.kind == MSV_U1 ? 8 : g.kind == MSV_U2 ? 32 : 0;
+            for (int j = 0; j < nm; ++j) {
+                uint64_t v;
+                memcpy(&v, g.mat + j, 8);
+                key.push_back(v);
+            }
         }
-        if (relabel) restore_order(passes, pos, o);
+        const bool hit = s->plan_cache && key == s->plan_key && s->plan_low.ok;
+        if (!hit) {
+            std::vector<Pass> passes;
+            std::vector<int> pos;
+            std::vector<Prim> renamed;
+            if (relabel) renamed = relabel_swaps(prims, s->n, pos);
+            const std::vector<Prim> &pl = relabel ? renamed : prims;
+            if (tune) {
+                int k = o.k_max, tb = o.tb;
+                if ((st = autotune(s->is_double(), s->stream(), pl, s->n, &k, &tb, &passes))) return st;
+                o.k_max = s->tuned_k = k;
+                o.tb = s->tuned_tb = tb;
+            } else {
+                passes = plan_passes(pl, o);
+            }
+            if (relabel) restore_order(passes, pos, o);
+            s->plan_key.clear();
+            s->plan_passes = std::move(passes);
+            s->plan_opts = o;
+            lower_for(s, s->plan_passes, o, s->plan_low);
+            if (s->plan_cache) s->plan_key = std::move(key);
+        }
+        o = s->plan_opts;
+        const std::vector<Pass> &passes = s->plan_passes;
         size_t n_ops = 0;
         for (auto &p : passes) n_ops += p.ops.size();
         double norm = 0.0, err_last = 0.0, words = 0.0;
@@ -638,7 +678,7 @@ int msv_apply(msv_sim *s, const msv_gate *gates, size_t n_gates)
         HIPCHK(s, hipEventCreate(&e0));
         HIPCHK(s, hipEventCreate(&e1));
         HIPCHK(s, hipEventRecord(e0, s->stream()));
-        st = run_passes_device(s, passes, o, &norm, &err_last, &words, nullptr);
+        st = run_passes_device(s, passes, o, &norm, &err_last, &words, nullptr, &s->plan_low);
         if (st == MSV_OK) {
             HIPCHK(s, hipEventRecord(e1, s->stream()));
             HIPCHK(s, hipEventSynchronize(e1));

@@ -22,7 +22,10 @@ int pin_stage(msv_sim *s, size_t bytes);
 // Run passes over the device-resident state (plain or compressed). Per-pass
 // (norm, max error, words) triples go to per_pass when given.
 int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOptions &o, double *norm_last,
-                      double *err_last, double *words_last, std::vector<double> *per_pass);
+                      double *err_last, double *words_last, std::vector<double> *per_pass,
+                      const Lowered *pre = nullptr);
+// Lower passes for the state's real type.
+void lower_for(const msv_sim *s, const std::vector<Pass> &passes, const PlanOptions &o, Lowered &low);
 
 // Autotuner: fusion width and tile size minimising the calibrated cost model.
 int autotune(bool is_double, hipStream_t stream, const std::vector<Prim> &prims, int n, int *k_out, int *tb_out,

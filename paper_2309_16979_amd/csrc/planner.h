@@ -86,6 +86,15 @@ void restore_order(std::vector<Pass> &passes, const std::vector<int> &pos, const
 // Partition prims (in list order) into passes and fuse each pass's ops.
 std::vector<Pass> plan_passes(const std::vector<Prim> &prims, const PlanOptions &o);
 
+// Passes lowered to device descriptors (one of poolf / poold is used).
+struct Lowered {
+    std::vector<OpDesc> ops;
+    std::vector<float> poolf;
+    std::vector<double> poold;
+    std::vector<PassGeom> geoms;
+    bool ok = false;
+};
+
 // Lower passes into device descriptors. The pool holds complex entries of the
 // state's real type (2 reals each). Geometry entries get op_begin / n_ops /
 // tile_q / nontile_mask / n_tiles filled.

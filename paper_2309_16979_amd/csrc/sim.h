@@ -84,6 +84,14 @@ struct msv_sim {
     int segments = 1;                // register segments in pass kernels
     int relabel = 1;                 // SWAPs of block-index qubits as relabelling (compressed device store)
     int tuned_k = 0, tuned_tb = 0;   // last autotuner choice
+    // Offline-stage result of the last device-store msv_apply: the passes and
+    // their lowered descriptors, reused when the next call brings the same
+    // gates under the same options (plan_key holds both, compared exactly).
+    std::vector<uint64_t> plan_key;
+    std::vector<msv::Pass> plan_passes;
+    msv::PlanOptions plan_opts;
+    msv::Lowered plan_low;
+    int plan_cache = 1;
     void *(*alloc)(size_t, void *) = nullptr;
     void (*dealloc)(void *, void *) = nullptr;
     void *actx = nullptr;

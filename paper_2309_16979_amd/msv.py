@@ -130,6 +130,10 @@ class Simulator:
         return check(code, self.h)
 
     # -- state
+    def set_option(self, key: str, value: float):
+        """msv_set_option on this handle (options that may change after init)."""
+        self._chk(self._L.msv_set_option(self.h, key.encode(), float(value)))
+
     def init_basis(self, index: int = 0):
         self._chk(self._L.msv_init_basis(self.h, int(index)))
 
