@@ -20,19 +20,35 @@ _MMA = {"f64": L.MMA_F64, "f32": L.MMA_F32, "bf16": L.MMA_BF16}
 _STORE = {"device": L.STORE_DEVICE, "host": L.STORE_HOST_PINNED}
 
 
+_GATE_DT = np.dtype({"names": ["kind", "q0", "q1", "theta", "param", "mat"],
+                     "formats": [np.uint32, np.int32, np.int32, np.float64, np.int32, np.uint64],
+                     "offsets": [L.Gate.kind.offset, L.Gate.q0.offset, L.Gate.q1.offset, L.Gate.theta.offset,
+                                 L.Gate.param.offset, L.Gate.mat.offset],
+                     "itemsize": C.sizeof(L.Gate)})
+
+
 def gate_array(gates: Sequence):
-    """Marshal gate records (name, q0, q1, theta, param, mat) into msv_gate[]."""
-    arr = (L.Gate * max(1, len(gates)))()
-    keep = []
-    for i, g in enumerate(gates):
-        m = None
-        if getattr(g, "mat", None) is not None:
-            v = np.asarray(g.mat, dtype=np.complex128).ravel()
-            buf = np.ascontiguousarray(np.stack([v.real, v.imag], axis=1).ravel())
-            keep.append(buf)
-            m = buf.ctypes.data_as(C.POINTER(C.c_double))
-        arr[i] = L.Gate(L.KINDS[g.name], int(g.q0), int(g.q1), float(g.theta),
-                        int(getattr(g, "param", -1)), m)
+    """Marshal gate records (name, q0, q1, theta, param, mat) into msv_gate[].
+
+    The records are filled column by column in a NumPy structured array laid
+    out as msv_gate; the returned ctypes array is a view of it (kept alive,
+    with the matrix buffers, by the second return value)."""
+    n = len(gates)
+    rec = np.zeros(max(1, n), dtype=_GATE_DT)
+    keep = [rec]
+    if n:
+        rec["kind"][:n] = [L.KINDS[g.name] for g in gates]
+        rec["q0"][:n] = [g.q0 for g in gates]
+        rec["q1"][:n] = [g.q1 for g in gates]
+        rec["theta"][:n] = [g.theta for g in gates]
+        rec["param"][:n] = [getattr(g, "param", -1) for g in gates]
+        for i, g in enumerate(gates):
+            if getattr(g, "mat", None) is not None:
+                v = np.asarray(g.mat, dtype=np.complex128).ravel()
+                buf = np.ascontiguousarray(np.stack([v.real, v.imag], axis=1).ravel())
+                keep.append(buf)
+                rec["mat"][i] = buf.ctypes.data
+    arr = (L.Gate * max(1, n)).from_buffer(rec)
     return arr, keep
 
 
