@@ -224,6 +224,30 @@ __device__ __forceinline__ void unpack_codes4(const uint64_t *m, const uint32_t 
     for (int p = 0; p < 4; ++p) q[p] = (int32_t)((uint32_t)A[p] + d[p]);
 }
 
+// unpack_codes4 with the words staged in LDS: stage[32 p + k] holds word k
+// of block p (0 at or beyond its width). Each plane word then reaches all
+// lanes by one broadcast LDS read instead of two v_readlane.
+__device__ __forceinline__ void unpack_codes4_lds(const uint64_t *stage, const uint32_t *W, const int32_t *A,
+                                                  int32_t *q)
+{
+    const uint32_t up = 63u - lane_id();
+    const uint32_t Wm = max(max(W[0], W[1]), max(W[2], W[3]));
+    uint32_t u[4] = {0u, 0u, 0u, 0u};
+    for (uint32_t k = Wm; k-- > 0;) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const uint64_t t = stage[32 * p + k] << up;
+            u[p] = __builtin_amdgcn_alignbit(u[p], (uint32_t)(t >> 32), 31u);
+        }
+    }
+    uint32_t d[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) d[p] = (u[p] >> 1) ^ (0u - (u[p] & 1u));
+    if (Wm) wave_inclusive_sum4(d);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) q[p] = (int32_t)((uint32_t)A[p] + d[p]);
+}
+
 // Lane k (< W[p]) receives bit-plane word k of block p, for four blocks.
 __device__ __forceinline__ void pack_planes4(const uint32_t *u, const uint32_t *W, uint64_t *mine)
 {

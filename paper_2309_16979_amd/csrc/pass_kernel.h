@@ -37,7 +37,13 @@ __device__ __forceinline__ void pass_tile(const PassGeom &geo, const PassBuffers
     __shared__ int32_t sA[NSB];
     __shared__ uint32_t sOff[NSB];
     __shared__ double sred[2 * NW];
-    __shared__ T sph[PhaseScratch<TB>::size];
+    // phase-op tables during the ops, plane-word staging (128 words per
+    // wave) during the decode
+    constexpr int SX = (PhaseScratch<TB>::size * (int)sizeof(T) + 7) / 8 > 128 * NW
+                           ? (PhaseScratch<TB>::size * (int)sizeof(T) + 7) / 8
+                           : 128 * NW;
+    __shared__ uint64_t sx[SX];
+    T *const sph = reinterpret_cast<T *>(sx);
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform for the compiler
@@ -46,7 +52,7 @@ __device__ __forceinline__ void pass_tile(const PassGeom &geo, const PassBuffers
     __syncthreads();
 
     const double sc = buf.scale_src ? 1.0 / __builtin_sqrt(*buf.scale_src) : buf.scale;
-    tile_load<T, TB, LOADC>(sre, sim, sG, buf.amps_in, buf.in, buf.step, sc, wave, lane);
+    tile_load<T, TB, LOADC>(sre, sim, sG, buf.amps_in, buf.in, buf.step, sc, wave, lane, sx + 128 * wave);
     __syncthreads();
 
     const T *pool = (const T *)buf.pool;
