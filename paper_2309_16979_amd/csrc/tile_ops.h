@@ -92,9 +92,9 @@ __device__ __forceinline__ void tile_blocks(const PassGeom &geo, uint64_t base, 
 
 // ------------------------------------------------------------------ load
 
-// stage: when not null, 128 words of LDS for this wave (the compressed
-// decode broadcasts plane words through it; see unpack_codes4_lds).
-template <typename T, int TB, bool LOADC>
+// STAGE: `stage` is 128 words of LDS for this wave, through which the
+// compressed decode broadcasts plane words (unpack_codes4_lds).
+template <typename T, int TB, bool LOADC, bool STAGE = false>
 __device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, const void *amps, const BlockStore &in,
                                           double step, double sc, int wave, int lane, uint64_t *stage = nullptr)
 {
@@ -163,7 +163,7 @@ __device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, co
                     W4[p] = (uint32_t)__builtin_amdgcn_readlane((int)wv, 2 * a + p);
                     A4[p] = __builtin_amdgcn_readlane(av, 2 * a + p);
                 }
-                if (stage) {
+                if constexpr (STAGE) {
                     if (lane < 32) {
 #pragma unroll
                         for (int p = 0; p < 4; ++p) stage[32 * p + lane] = mine[2 * a + p];
