@@ -126,8 +126,8 @@ def cpu_baseline(n, x, gates, seconds):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(sharding is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(a state is not sharded across GPUs); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
