@@ -160,10 +160,10 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, Bloc
             if (fast) {
                 // all kFastTerms slots (tl is 0 beyond n_terms): no branch per
                 // term, one scalar bit test and select per sign
-                const uint64_t neg = __ballot((__popcll(G & mhi) & 1) != 0);
+                const uint32_t neg = (uint32_t)__ballot((__popcll(G & mhi) & 1) != 0);   // lanes < 32 hold terms
 #pragma unroll
                 for (int t = 0; t < kFastTerms; ++t) {
-                    const double sg = ((neg >> t) & 1ull) ? -1.0 : 1.0;
+                    const double sg = ((neg >> t) & 1u) ? -1.0 : 1.0;
                     v = __builtin_fma(sg, tl[t], v);
                 }
             } else {
@@ -237,13 +237,17 @@ hipError_t launch_reduce_final(const double *partials, int n_groups, double *out
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(kThreads) void pass_stats_kernel(const double *part, const uint64_t *offs,
-                                                              double *out)
+// One workgroup of kStatThreads per pass (a pass has up to 2^(n - TB)
+// workgroup partials, 65536 at n = 28).
+constexpr int kStatThreads = 1024;
+
+__global__ __launch_bounds__(kStatThreads) void pass_stats_kernel(const double *part, const uint64_t *offs,
+                                                                  double *out)
 {
-    __shared__ double sn[kThreads], se[kThreads], sw[kThreads];
+    __shared__ double sn[kStatThreads], se[kStatThreads], sw[kStatThreads];
     const int p = blockIdx.x;
     double a = 0.0, e = 0.0, w = 0.0;
-    for (uint64_t i = offs[p] + threadIdx.x; i < offs[p + 1]; i += kThreads) {
+    for (uint64_t i = offs[p] + threadIdx.x; i < offs[p + 1]; i += kStatThreads) {
         a += part[3 * i];
         e = fmax(e, part[3 * i + 1]);
         w += part[3 * i + 2];
@@ -252,7 +256,7 @@ __global__ __launch_bounds__(kThreads) void pass_stats_kernel(const double *part
     se[threadIdx.x] = e;
     sw[threadIdx.x] = w;
     __syncthreads();
-    for (int h = kThreads / 2; h >= 1; h >>= 1) {
+    for (int h = kStatThreads / 2; h >= 1; h >>= 1) {
         if ((int)threadIdx.x < h) {
             sn[threadIdx.x] += sn[threadIdx.x + h];
             se[threadIdx.x] = fmax(se[threadIdx.x], se[threadIdx.x + h]);
@@ -267,7 +271,7 @@ hipError_t launch_pass_stats(const double *part, const uint64_t *pass_offsets, i
                              hipStream_t stream)
 {
     if (n_passes <= 0) return hipSuccess;
-    hipLaunchKernelGGL(pass_stats_kernel, dim3(n_passes), dim3(kThreads), 0, stream, part, pass_offsets, out);
+    hipLaunchKernelGGL(pass_stats_kernel, dim3(n_passes), dim3(kStatThreads), 0, stream, part, pass_offsets, out);
     return hipGetLastError();
 }
 
