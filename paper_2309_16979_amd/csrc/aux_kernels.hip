@@ -57,8 +57,11 @@ constexpr int kRedGroups = 2048;
 // fetches the metadata of round block a, plane p, then every block's payload
 // word `lane` is loaded before one wait. f(G, xr, xi) runs per decoded block.
 template <typename T, bool COMP, typename F>
+// stage: 128 words of LDS for this wave, through which the decode broadcasts
+// plane words (unpack_codes4_lds).
 static __device__ __forceinline__ void for_amp_blocks(const void *amps, const BlockStore &st, double step,
-                                                      uint64_t first, uint64_t nab, int wave, int lane, F &&f)
+                                                      uint64_t first, uint64_t nab, int wave, int lane,
+                                                      uint64_t *stage, F &&f)
 {
     using V2 = typename Vec2<T>::V;
     constexpr int NW = kThreads / 64;
@@ -111,7 +114,11 @@ static __device__ __forceinline__ void for_amp_blocks(const void *amps, const Bl
                 W4[p] = (uint32_t)__builtin_amdgcn_readlane((int)wv, 2 * a + p);
                 A4[p] = __builtin_amdgcn_readlane(av, 2 * a + p);
             }
-            unpack_codes4(mine + 2 * a, W4, A4, q4);
+            if (lane < 32) {
+#pragma unroll
+                for (int p = 0; p < 4; ++p) stage[32 * p + lane] = mine[2 * a + p];
+            }
+            unpack_codes4_lds(stage, W4, A4, q4);
             f(first + k, (double)dequantize<T>(q4[0], step), (double)dequantize<T>(q4[1], step));
             if (k + stride < nab)
                 f(first + k + stride, (double)dequantize<T>(q4[2], step), (double)dequantize<T>(q4[3], step));
@@ -147,7 +154,9 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, Bloc
                                   : 0.0;
         if (lane < a.n_terms) mhi = a.masks[lane] >> 6;
     }
-    for_amp_blocks<T, COMP>(amps, st, step, first, nab, wave, lane, [&](uint64_t G, double xr, double xi) {
+    __shared__ uint64_t stage[NW * 128];
+    for_amp_blocks<T, COMP>(amps, st, step, first, nab, wave, lane, stage + 128 * wave,
+                            [&](uint64_t G, double xr, double xi) {
         xr *= a.scale;
         xi *= a.scale;
         const uint64_t i = (G << 6) | (uint64_t)lane;
@@ -284,7 +293,10 @@ __global__ __launch_bounds__(kThreads) void decode_range_kernel(BlockStore st, d
     using V2 = typename Vec2<T>::V;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for_amp_blocks<T, true>(nullptr, st, step, first, nab, wave, lane, [&](uint64_t G, double xr, double xi) {
+    constexpr int NW = kThreads / 64;
+    __shared__ uint64_t stage[NW * 128];
+    for_amp_blocks<T, true>(nullptr, st, step, first, nab, wave, lane, stage + 128 * wave,
+                            [&](uint64_t G, double xr, double xi) {
         V2 v;
         v.x = (T)xr;
         v.y = (T)xi;
