@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from tests.gpu_util import ensure_built, log, max_abs
-from workloads import ghz, random_circuit, qft_plus_random, zz_chain
+from workloads import Gate, ghz, random_circuit, qft_plus_random, zz_chain
 
 pytestmark = pytest.mark.gpu
 
@@ -147,3 +147,25 @@ def test_host_store_ghz_exact_many_chunks():
     assert np.all(a0[1:] == 0) and np.all(a1[:-1] == 0)
     assert len(zero) == 32 and oracle.codec_header(zero)["kind"] == 0
     assert st["compressed_bytes"] < 200 * (1 << (n - lc))
+
+
+@pytest.mark.parametrize("eb,amp", [(4.66e-10, 0.9), (1e-9, 0.01)])
+def test_wide_blocks_through_pass_kernels(eb, amp):
+    """Codes up to 0.9 / (2 eb) = 9.7e8 (block widths of 32 bit planes) through the
+    pass kernels' decode and encode: Z on qubit 0 twice is the identity with
+    exact +-1 factors, so complex128 states come back bit-identical to the
+    oracle codec's decode of the initial state."""
+    n = 12
+    rng = np.random.default_rng(31)
+    v = (rng.uniform(-amp, amp, 1 << n) + 1j * rng.uniform(-amp, amp, 1 << n)).astype(np.complex128)
+    ref = oracle.codec_decode(oracle.codec_encode(v, n, eb))
+    log("wide blocks", eb)
+    with _sim(n, "c128", eb, chunk_qubits=n) as s:
+        s.init_state(v)
+        s.apply([Gate("Z", 0), Gate("Z", 0)])
+        assert s.stats()["passes"] >= 1
+        got = s.amplitudes()
+        chunk = s.export_chunk(0)
+    assert np.array_equal(got.view(np.uint8), ref.view(np.uint8))
+    widths = np.frombuffer(chunk, dtype=np.uint8)[32:32 + 2 * (1 << n) // 64]
+    assert widths.max() >= (30 if eb < 1e-9 else 20)
