@@ -31,6 +31,10 @@ __device__ __forceinline__ ConstPtr<T> as_const(const T *p)
 }
 
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ float absT(float a) { return __builtin_fabsf(a); }
+__device__ __forceinline__ double absT(double a) { return __builtin_fabs(a); }
+__device__ __forceinline__ float maxT(float a, float b) { return __builtin_fmaxf(a, b); }
+__device__ __forceinline__ double maxT(double a, double b) { return __builtin_fmax(a, b); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 __device__ __forceinline__ uint64_t block_index(const BlockStore &s, uint64_t B)
@@ -229,6 +233,11 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
         return 0;
     }
     bool bad = false;
+    // |x - x'| in T is exact: x' = 0 when the code is 0, and otherwise x and
+    // x' have the same sign and are within a factor of two of each other
+    // (|x - q step| <= step / 2 with |q| >= 1), so the subtraction loses
+    // nothing (Sterbenz). The FP64 maximum equals the maximum taken in T.
+    T errt = 0;
     // E1 (per amplitude block, both planes): codes, residuals, widths; the
     // zigzag residuals replace the values in LDS. Two amplitude blocks per
     // iteration when the wave has an even number of them (independent
@@ -250,7 +259,7 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const T yr = dequantize<T>(q[2 * h], step), yi = dequantize<T>(q[2 * h + 1], step);
-                err = fmax(err, fmax(__builtin_fabs(d[2 * h] - (double)yr), __builtin_fabs(d[2 * h + 1] - (double)yi)));
+                errt = maxT(errt, maxT(absT(x[2 * h] - yr), absT(x[2 * h + 1] - yi)));
             }
         }
         uint32_t u[4], W4[4];
@@ -281,7 +290,7 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
         const int32_t qi = quantize<T>(xi, inv_step, bad);
         if (check) {
             const T yr = dequantize<T>(qr, step), yi = dequantize<T>(qi, step);
-            err = fmax(err, fmax(__builtin_fabs(dr - (double)yr), __builtin_fabs(di - (double)yi)));
+            errt = maxT(errt, maxT(absT(xr - yr), absT(xi - yi)));
         }
         const uint32_t ur = residual_zigzag(qr);
         const uint32_t ui = residual_zigzag(qi);
@@ -298,6 +307,7 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
             sA[2 * jb + 1] = Ai;
         }
     }
+    err = fmax(err, (double)errt);
     if (bad) atomicOr(flags, 1u);
     __syncthreads();
     // E2: exclusive scan of the widths over the tile's blocks
