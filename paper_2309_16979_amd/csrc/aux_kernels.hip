@@ -126,8 +126,6 @@ static __device__ __forceinline__ void for_amp_blocks(const void *amps, const Bl
     }
 }
 
-constexpr int kFastTerms = 32;
-
 template <typename T, bool COMP>
 __global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, BlockStore st, double step,
                                                           ReduceArgs a)
@@ -138,21 +136,21 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, Bloc
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t nab = a.amp_count >> 6, first = a.amp_begin >> 6;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    // Z-strings: the sign of term t at index i = (G << 6) | lane factors into a
-    // lane part, folded into tl[t] = c_t (-1)^popcount(lane & m_t) once, and a
-    // block part (-1)^popcount(G & (m_t >> 6)), the same for the whole block:
-    // lane t evaluates it for term t and one ballot hands every block sign to
-    // the wave as a scalar bit mask.
-    const bool fast = a.kind == RED_EXPZ && a.n_terms <= kFastTerms;
-    double tl[kFastTerms];
-    uint64_t mhi = 0;
-    if (fast) {
-#pragma unroll
-        for (int t = 0; t < kFastTerms; ++t)
-            tl[t] = t < a.n_terms ? ((__popc((uint32_t)(a.masks[t] & 63u) & (uint32_t)lane) & 1) ? -a.coeffs[t]
-                                                                                                 : a.coeffs[t])
-                                  : 0.0;
-        if (lane < a.n_terms) mhi = a.masks[lane] >> 6;
+    // Z-strings (up to 64 terms): per block G (64 amplitudes, lane = index
+    // bits 0..5) the expectation is sum_t c_t (-1)^popcount(G & h_t) P^(l_t),
+    // with l_t / h_t the low 6 / high bits of mask m_t and P^ the 64-point
+    // Walsh-Hadamard transform of the block's probabilities over the lanes,
+    // P^(l) = sum_j p_j (-1)^popcount(l & j). Six butterfly stages leave P^(l)
+    // in lane l; lane t then gathers P^(l_t) for term t and weights it with
+    // its own block sign, so the cost per block does not grow with the terms.
+    const bool fast = a.kind == RED_EXPZ && a.n_terms <= 64;
+    double ct = 0.0;        // lane t: coefficient of term t (0 beyond n_terms)
+    uint64_t mhi = 0;       // lane t: block-index part of m_t
+    int lsrc = 0;           // lane t: l_t, the lane holding P^(l_t)
+    if (fast && lane < a.n_terms) {
+        ct = a.coeffs[lane];
+        mhi = a.masks[lane] >> 6;
+        lsrc = (int)(a.masks[lane] & 63u);
     }
     __shared__ uint64_t stage[NW * 128];
     for_amp_blocks<T, COMP>(amps, st, step, first, nab, wave, lane, stage + 128 * wave,
@@ -165,21 +163,21 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, Bloc
         if (a.kind == RED_PROB1) {
             if ((i >> a.qubit) & 1ull) acc[1] += p;
         } else if (a.kind == RED_EXPZ) {
-            double v = 0.0;
             if (fast) {
-                // all kFastTerms slots (tl is 0 beyond n_terms): no branch per
-                // term, one scalar bit test and select per sign
-                const uint32_t neg = (uint32_t)__ballot((__popcll(G & mhi) & 1) != 0);   // lanes < 32 hold terms
+                double P = p;
 #pragma unroll
-                for (int t = 0; t < kFastTerms; ++t) {
-                    const double sg = ((neg >> t) & 1u) ? -1.0 : 1.0;
-                    v = __builtin_fma(sg, tl[t], v);
+                for (int d = 1; d < 64; d <<= 1) {
+                    const double o = __shfl_xor(P, d, 64);
+                    P = (lane & d) ? o - P : P + o;
                 }
+                const double ph = __shfl(P, lsrc, 64);
+                acc[1] += ((__popcll(G & mhi) & 1) ? -ct : ct) * ph;
             } else {
+                double v = 0.0;
                 for (int t = 0; t < a.n_terms; ++t)
                     v += (__popcll(i & a.masks[t]) & 1) ? -a.coeffs[t] : a.coeffs[t];
+                acc[1] += p * v;
             }
-            acc[1] += p * v;
         } else if (a.kind == RED_OVERLAP) {
             const uint64_t r = i - a.amp_begin;
             const double rr = a.ref[2 * r], ri = a.ref[2 * r + 1];

@@ -119,7 +119,8 @@ __device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, co
         for (int i = 0; i < PER; ++i) {
             const int jb = wave + NW * i;
             if (jb < NAB) {
-                if (sc != 1.0) { v[i].x *= scale; v[i].y *= scale; }
+                v[i].x *= scale;   // exact when scale is 1
+                v[i].y *= scale;
                 const int p = swz(jb * 64 + lane);
                 sre[p] = v[i].x;
                 sim[p] = v[i].y;
@@ -179,7 +180,8 @@ __device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, co
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     T xr = dequantize<T>(q4[2 * h], step), xi = dequantize<T>(q4[2 * h + 1], step);
-                    if (sc != 1.0) { xr *= scale; xi *= scale; }
+                    xr *= scale;   // exact when scale is 1
+                    xi *= scale;
                     const int p = swz((jb + NW * h) * 64 + lane);
                     sre[p] = xr;
                     sim[p] = xi;
@@ -196,7 +198,8 @@ __device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, co
                               (uint32_t)__builtin_amdgcn_readlane((int)wv, 2 * a + 1),
                               __builtin_amdgcn_readlane(av, 2 * a + 1), qr, qi);
                 T xr = dequantize<T>(qr, step), xi = dequantize<T>(qi, step);
-                if (sc != 1.0) { xr *= scale; xi *= scale; }
+                xr *= scale;   // exact when scale is 1
+                xi *= scale;
                 const int p = swz(jb * 64 + lane);
                 sre[p] = xr;
                 sim[p] = xi;

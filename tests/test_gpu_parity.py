@@ -147,3 +147,35 @@ def test_inverse_returns_basis_state():
     assert abs(a[777] - 1) <= 1e-12 * len(gates) * 2
     a[777] = 0
     assert np.max(np.abs(a)) <= 1e-12 * len(gates)
+
+
+@pytest.mark.parametrize("dtype,eb,n_terms", [("c128", 0.0, 1), ("c128", 0.0, 37), ("c128", 0.0, 64),
+                                              ("c128", 0.0, 65), ("c64", 1e-6, 50)])
+def test_expectation_many_terms(dtype, eb, n_terms):
+    """Z-string sums of up to 64 terms take the Walsh-Hadamard path (any low
+    and high mask bits, terms in every lane); 65 terms take the per-term one.
+    Against the oracle's state: exact for complex128 without compression; with
+    it, |<O>_got - <O>| <= sum|c| (2 e + e^2) for a state error of 2-norm e
+    <= p eb' sqrt(2 * 2^n) plus complex64 rounding."""
+    n = 15
+    gates = random_circuit(n, 10, seed=13)
+    psi = oracle.simulate(n, gates, 11)
+    rng = np.random.default_rng(n_terms)
+    masks = [int(m) for m in rng.integers(0, 1 << n, n_terms)]
+    masks[0] = 0   # the identity term
+    coeffs = [float(c) for c in rng.uniform(-2, 2, n_terms)]
+    ref = oracle.expect_z(n, psi, masks, coeffs)
+    log("expect terms", dtype, eb, n_terms)
+    from paper_2309_16979_amd import Simulator
+    with Simulator(n, dtype=dtype, eb=eb, chunk_qubits=12) as s:
+        s.init_basis(11)
+        s.apply(gates)
+        got = s.expect_z(masks, coeffs)
+        p = s.stats()["passes"]
+    csum = sum(abs(c) for c in coeffs)
+    if eb == 0.0:
+        tol = 1e-12 * csum
+    else:
+        e = p * (eb * (1 + 2.0 ** -20) + 2.0 ** -23) * math.sqrt(2.0 * (1 << n)) + len(gates) * 1e-6
+        tol = csum * (2 * e + e * e)
+    assert got == pytest.approx(ref, abs=tol)
