@@ -30,7 +30,13 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(PassGeom geo, Adjoint
     __shared__ int32_t sA[NSB];
     __shared__ uint32_t sOff[NSB];
     __shared__ double sred[4 * NW];
-    __shared__ T sph[PhaseScratch<TB>::size];
+    // phase-op tables during the ops, plane-word staging (128 words per
+    // wave) during the decode
+    constexpr int SX = (PhaseScratch<TB>::size * (int)sizeof(T) + 7) / 8 > 128 * NW
+                           ? (PhaseScratch<TB>::size * (int)sizeof(T) + 7) / 8
+                           : 128 * NW;
+    __shared__ uint64_t sx[SX];
+    T *const sph = reinterpret_cast<T *>(sx);
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -38,8 +44,10 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(PassGeom geo, Adjoint
     const uint64_t base = tile_base(geo, tile);
     tile_blocks<TB>(geo, base, sG);
     __syncthreads();
-    tile_load<T, TB, COMP>(pre, pim, sG, buf.psi.amps_in, buf.psi.in, buf.psi.step, 1.0, wave, lane);
-    tile_load<T, TB, COMP>(lre, lim, sG, buf.lam.amps_in, buf.lam.in, buf.lam.step, 1.0, wave, lane);
+    tile_load<T, TB, COMP, true>(pre, pim, sG, buf.psi.amps_in, buf.psi.in, buf.psi.step, 1.0, wave, lane,
+                                 sx + 128 * wave);
+    tile_load<T, TB, COMP, true>(lre, lim, sG, buf.lam.amps_in, buf.lam.in, buf.lam.step, 1.0, wave, lane,
+                                 sx + 128 * wave);
     __syncthreads();
 
     const T *pool = (const T *)buf.psi.pool;
