@@ -37,8 +37,8 @@ __device__ __forceinline__ void pass_tile(const PassGeom &geo, const PassBuffers
     __shared__ int32_t sA[NSB];
     __shared__ uint32_t sOff[NSB];
     __shared__ double sred[2 * NW];
-    // phase-op tables during the ops, plane-word staging (128 words per
-    // wave) during the decode
+    // phase-op tables during the ops; per wave, 128 words of plane-word
+    // staging during the decode and payload offsets during the encode
     constexpr int SX = (PhaseScratch<TB>::size * (int)sizeof(T) + 7) / 8 > 128 * NW
                            ? (PhaseScratch<TB>::size * (int)sizeof(T) + 7) / 8
                            : 128 * NW;
@@ -85,9 +85,11 @@ __device__ __forceinline__ void pass_tile(const PassGeom &geo, const PassBuffers
 
     double nrm = 0.0, err = 0.0;
     const uint64_t slot = (tile - buf.slot_tile0) * (uint64_t)(32 * NSB);
-    const uint32_t words = tile_store<T, TB, STOREC>(sre, sim, sG, sW, sA, sOff, buf.amps_out, buf.out, slot,
-                                                     buf.inv_step, buf.step, buf.check_err, buf.flags, nrm, err,
-                                                     wave, lane);
+    static_assert(NSB <= 256, "per-wave offsets hold 256 words");
+    const uint32_t words = tile_store<T, TB, STOREC, true>(sre, sim, sG, sW, sA, sOff, buf.amps_out, buf.out, slot,
+                                                           buf.inv_step, buf.step, buf.check_err, buf.flags, nrm,
+                                                           err, wave, lane,
+                                                           reinterpret_cast<uint32_t *>(sx + 128 * wave));
     // per-workgroup statistics (fixed reduction order)
     nrm = wave_sum_f64(nrm);
     err = wave_max_f64(err);

@@ -213,11 +213,15 @@ __device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, co
 // Store the tile (plain or encoded). nrm / err accumulate this thread's FP64
 // sum |x|^2 and max |x - x'|; the return value is the tile's payload words
 // (valid in every thread). The codec scratch sW / sA / sOff holds NSB entries.
-template <typename T, int TB, bool STOREC>
+// OWN_OFF: `own_off` (2^(TB-5) words of LDS for this wave) receives the
+// payload offsets: every wave scans the widths itself (E2), so E3 needs no
+// second barrier. Otherwise wave 0 scans into sOff.
+template <typename T, int TB, bool STOREC, bool OWN_OFF = false>
 __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *sG, uint32_t *sW, int32_t *sA,
                                                uint32_t *sOff, void *amps, const BlockStore &out, uint64_t slot,
                                                double inv_step, double step, int check, uint32_t *flags,
-                                               double &nrm, double &err, int wave, int lane)
+                                               double &nrm, double &err, int wave, int lane,
+                                               uint32_t *own_off = nullptr)
 {
     constexpr int NAB = 1 << (TB - 6), NSB = 2 * NAB, NW = kThreads / 64;
     constexpr int VPT = sizeof(T) / 4;
@@ -314,7 +318,8 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
     if (bad) atomicOr(flags, 1u);
     __syncthreads();
     // E2: exclusive scan of the widths over the tile's blocks
-    if (wave == 0) {
+    uint32_t *const so = OWN_OFF ? own_off : sOff;
+    if (OWN_OFF || wave == 0) {
         constexpr int PER = (NSB + 63) / 64;
         uint32_t v[PER];
         uint32_t s = 0;
@@ -328,11 +333,11 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int idx = lane * PER + i;
-            if (idx < NSB) sOff[idx] = ex;
+            if (idx < NSB) so[idx] = ex;
             ex += v[i];
         }
     }
-    __syncthreads();
+    if (!OWN_OFF) __syncthreads();
     // E3: bit planes of both planes into this tile's heap slot; then lane j
     // of the wave writes width, anchor and offset of the wave's stream block j
     if constexpr (NAB % (2 * NW) == 0) {
@@ -346,7 +351,7 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
             const uint32_t W4[4] = {sW[2 * jb], sW[2 * jb + 1], sW[2 * jc], sW[2 * jc + 1]};
             uint64_t m[4];
             pack_planes4(u, W4, m);
-            const uint32_t o4[4] = {sOff[2 * jb], sOff[2 * jb + 1], sOff[2 * jc], sOff[2 * jc + 1]};
+            const uint32_t o4[4] = {so[2 * jb], so[2 * jb + 1], so[2 * jc], so[2 * jc + 1]};
 #pragma unroll
             for (int p = 0; p < 4; ++p)
                 if ((uint32_t)lane < W4[p]) out.heap[slot + o4[p] + lane] = m[p];
@@ -359,8 +364,8 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
             const uint32_t Wr = sW[2 * jb], Wi = sW[2 * jb + 1];
             const uint64_t mr = pack_planes(ur, Wr);
             const uint64_t mi = pack_planes(ui, Wi);
-            if ((uint32_t)lane < Wr) out.heap[slot + sOff[2 * jb] + lane] = mr;
-            if ((uint32_t)lane < Wi) out.heap[slot + sOff[2 * jb + 1] + lane] = mi;
+            if ((uint32_t)lane < Wr) out.heap[slot + so[2 * jb] + lane] = mr;
+            if ((uint32_t)lane < Wi) out.heap[slot + so[2 * jb + 1] + lane] = mi;
         }
     }
     constexpr int APW = (NAB + NW - 1) / NW;
@@ -372,10 +377,10 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
             const uint64_t bi = block_index(out, 2 * sG[jb] + (uint64_t)(j & 1));
             out.W[bi] = (uint8_t)sW[bt];
             out.A[bi] = sA[bt];
-            out.OFF[bi] = (uint32_t)(slot + sOff[bt]);
+            out.OFF[bi] = (uint32_t)(slot + so[bt]);
         }
     }
-    return sOff[NSB - 1] + sW[NSB - 1];
+    return so[NSB - 1] + sW[NSB - 1];
 }
 
 // ------------------------------------------------------------------- ops
