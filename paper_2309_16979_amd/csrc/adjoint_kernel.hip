@@ -44,9 +44,9 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(PassGeom geo, Adjoint
     const uint64_t base = tile_base(geo, tile);
     tile_blocks<TB>(geo, base, sG);
     __syncthreads();
-    tile_load<T, TB, COMP, true>(pre, pim, sG, buf.psi.amps_in, buf.psi.in, buf.psi.step, 1.0, wave, lane,
+    tile_load<T, TB, COMP>(pre, pim, sG, buf.psi.amps_in, buf.psi.in, buf.psi.step, 1.0, wave, lane,
                                  sx + 128 * wave);
-    tile_load<T, TB, COMP, true>(lre, lim, sG, buf.lam.amps_in, buf.lam.in, buf.lam.step, 1.0, wave, lane,
+    tile_load<T, TB, COMP>(lre, lim, sG, buf.lam.amps_in, buf.lam.in, buf.lam.step, 1.0, wave, lane,
                                  sx + 128 * wave);
     __syncthreads();
 

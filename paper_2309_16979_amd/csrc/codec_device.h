@@ -142,7 +142,8 @@ __device__ __forceinline__ void block_width2(uint32_t u, uint32_t v, uint32_t &w
 __device__ __forceinline__ void unpack_codes2(uint64_t mr, uint32_t Wr, int32_t Ar, uint64_t mi, uint32_t Wi,
                                               int32_t Ai, int32_t &qr, int32_t &qi)
 {
-    // planes from the most significant down, as in unpack_codes4
+    // planes from the most significant down: word << (63 - lane) puts this
+    // lane's bit on top, and a funnel shift appends it to u
     const uint32_t up = 63u - lane_id();
     const uint32_t Wm = Wr > Wi ? Wr : Wi;
     uint32_t ur = 0, ui = 0;
@@ -197,36 +198,11 @@ __device__ __forceinline__ void block_width4(const uint32_t *u_in, uint32_t *w)
     }
 }
 
-// Codes of four blocks (two amplitude blocks, both planes each). Lane k holds
-// word k of block p in m[p] and 0 for k at or beyond its width, so all four
-// unpack in one loop up to the largest width.
-__device__ __forceinline__ void unpack_codes4(const uint64_t *m, const uint32_t *W, const int32_t *A, int32_t *q)
-{
-    // Planes from the most significant down: word << (63 - lane) puts this
-    // lane's bit on top, and a funnel shift appends it to u.
-    const uint32_t up = 63u - lane_id();
-    const uint32_t Wm = max(max(W[0], W[1]), max(W[2], W[3]));
-    uint32_t u[4] = {0u, 0u, 0u, 0u};
-    for (uint32_t k = Wm; k-- > 0;) {
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const uint32_t w_lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)m[p], (int)k);
-            const uint32_t w_hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(m[p] >> 32), (int)k);
-            const uint64_t t = (((uint64_t)w_hi << 32) | w_lo) << up;
-            u[p] = __builtin_amdgcn_alignbit(u[p], (uint32_t)(t >> 32), 31u);
-        }
-    }
-    uint32_t d[4];
-#pragma unroll
-    for (int p = 0; p < 4; ++p) d[p] = (u[p] >> 1) ^ (0u - (u[p] & 1u));
-    if (Wm) wave_inclusive_sum4(d);
-#pragma unroll
-    for (int p = 0; p < 4; ++p) q[p] = (int32_t)((uint32_t)A[p] + d[p]);
-}
-
-// unpack_codes4 with the words staged in LDS: stage[32 p + k] holds word k
-// of block p (0 at or beyond its width). Each plane word then reaches all
-// lanes by one broadcast LDS read instead of two v_readlane.
+// Codes of four blocks (two amplitude blocks, both planes each), unpacked in
+// one loop up to the largest width. The words are staged in LDS:
+// stage[32 p + k] holds word k of block p (0 at or beyond its width), so each
+// plane word reaches all lanes by one broadcast LDS read instead of two
+// v_readlane. Planes go from the most significant down, as in unpack_codes2.
 __device__ __forceinline__ void unpack_codes4_lds(const uint64_t *stage, const uint32_t *W, const int32_t *A,
                                                   int32_t *q)
 {

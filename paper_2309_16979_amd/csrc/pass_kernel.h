@@ -52,7 +52,7 @@ __device__ __forceinline__ void pass_tile(const PassGeom &geo, const PassBuffers
     __syncthreads();
 
     const double sc = buf.scale_src ? 1.0 / __builtin_sqrt(*buf.scale_src) : buf.scale;
-    tile_load<T, TB, LOADC, true>(sre, sim, sG, buf.amps_in, buf.in, buf.step, sc, wave, lane, sx + 128 * wave);
+    tile_load<T, TB, LOADC>(sre, sim, sG, buf.amps_in, buf.in, buf.step, sc, wave, lane, sx + 128 * wave);
     __syncthreads();
 
     const T *pool = (const T *)buf.pool;

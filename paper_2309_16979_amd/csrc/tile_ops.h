@@ -96,11 +96,11 @@ __device__ __forceinline__ void tile_blocks(const PassGeom &geo, uint64_t base, 
 
 // ------------------------------------------------------------------ load
 
-// STAGE: `stage` is 128 words of LDS for this wave, through which the
-// compressed decode broadcasts plane words (unpack_codes4_lds).
-template <typename T, int TB, bool LOADC, bool STAGE = false>
+// stage: 128 words of LDS for this wave, through which the compressed decode
+// broadcasts plane words (unpack_codes4_lds).
+template <typename T, int TB, bool LOADC>
 __device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, const void *amps, const BlockStore &in,
-                                          double step, double sc, int wave, int lane, uint64_t *stage = nullptr)
+                                          double step, double sc, int wave, int lane, uint64_t *stage)
 {
     constexpr int NAB = 1 << (TB - 6), NSB = 2 * NAB, NW = kThreads / 64;
     using V2 = typename Cplx<T>::V;
@@ -168,15 +168,11 @@ __device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, co
                     W4[p] = (uint32_t)__builtin_amdgcn_readlane((int)wv, 2 * a + p);
                     A4[p] = __builtin_amdgcn_readlane(av, 2 * a + p);
                 }
-                if constexpr (STAGE) {
-                    if (lane < 32) {
+                if (lane < 32) {
 #pragma unroll
-                        for (int p = 0; p < 4; ++p) stage[32 * p + lane] = mine[2 * a + p];
-                    }
-                    unpack_codes4_lds(stage, W4, A4, q4);
-                } else {
-                    unpack_codes4(mine + 2 * a, W4, A4, q4);
+                    for (int p = 0; p < 4; ++p) stage[32 * p + lane] = mine[2 * a + p];
                 }
+                unpack_codes4_lds(stage, W4, A4, q4);
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     T xr = dequantize<T>(q4[2 * h], step), xi = dequantize<T>(q4[2 * h + 1], step);
