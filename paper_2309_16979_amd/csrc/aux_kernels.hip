@@ -387,6 +387,59 @@ static __device__ uint64_t block_exclusive_scan(uint64_t v, uint64_t *ex, uint64
     return total;
 }
 
+// Block-wide sum of one uint64 per thread (every thread gets it).
+static __device__ uint64_t block_sum(uint64_t v, uint64_t *sbuf)
+{
+    uint64_t ex;
+    return block_exclusive_scan(v, &ex, sbuf);
+}
+
+// Four codec widths packed in a word: their sum (v_sad_u8 against zero) and
+// whether any of them exceeds 32 (a byte is > 32 when it is >= 64, or when
+// bit 5 is set together with any of bits 0..4).
+static __device__ __forceinline__ uint32_t width4_sum(uint32_t x, uint32_t acc)
+{
+    return __builtin_amdgcn_sad_u8(x, 0u, acc);
+}
+static __device__ __forceinline__ uint32_t width4_bad(uint32_t x)
+{
+    const uint32_t low = ((x & 0x1F1F1F1Fu) + 0x1F1F1F1Fu) & 0x20202020u;
+    return (x & 0xC0C0C0C0u) | (x & low);
+}
+
+// Sum of the widths w[0..n) over the workgroup's threads (per-thread part
+// returned; the caller reduces), with bit flags of widths above 32 in *bad.
+// n and the address of w must be multiples of 16 for the wide path.
+static __device__ __forceinline__ uint64_t widths_part(const uint8_t *w, uint64_t n, uint32_t *bad)
+{
+    uint64_t s = 0;
+    uint32_t b = 0;
+    if ((((uintptr_t)w) & 15u) == 0 && (n & 15u) == 0) {
+        const uint4 *w16 = reinterpret_cast<const uint4 *>(w);
+        for (uint64_t i = threadIdx.x; i < n / 16; i += kThreads) {
+            const uint4 x = w16[i];
+            uint32_t t = width4_sum(x.x, 0u);
+            t = width4_sum(x.y, t);
+            t = width4_sum(x.z, t);
+            t = width4_sum(x.w, t);
+            s += t;
+            b |= width4_bad(x.x) | width4_bad(x.y) | width4_bad(x.z) | width4_bad(x.w);
+        }
+    } else {
+        for (uint64_t i = threadIdx.x; i < n; i += kThreads) {
+            const uint32_t v = w[i];
+            s += v;
+            b |= v > 32 ? 1u : 0u;
+        }
+    }
+    *bad |= b;
+    return s;
+}
+
+// Grid: x = chunk, y = segment of the chunk's blocks. Each workgroup sums the
+// widths before its segment and scans its segment in tiles of kThreads
+// blocks; the first one also sums the whole chunk and decides its kind (all
+// widths and anchors zero: ZERO).
 __global__ __launch_bounds__(kThreads) void scan_chunks_kernel(const uint8_t *W, const int32_t *A, uint64_t nb,
                                                                uint32_t *off, uint64_t *sizes, uint32_t *kinds,
                                                                uint32_t *flags)
@@ -394,30 +447,44 @@ __global__ __launch_bounds__(kThreads) void scan_chunks_kernel(const uint8_t *W,
     __shared__ uint64_t sbuf[kThreads];
     __shared__ int snz;
     const uint64_t c = blockIdx.x;
+    const uint64_t seg_len = (nb + gridDim.y - 1) / gridDim.y;
+    const uint64_t s0 = (uint64_t)blockIdx.y * seg_len;
+    if (s0 >= nb) return;   // whole workgroup, before any barrier
+    const uint64_t s1 = s0 + seg_len < nb ? s0 + seg_len : nb;
+    const bool first = blockIdx.y == 0;
     const uint8_t *w = W + c * nb;
     const int32_t *a = A + c * nb;
-    const uint64_t per = (nb + kThreads - 1) / kThreads;
-    const uint64_t b0 = threadIdx.x * per, b1 = b0 + per < nb ? b0 + per : nb;
-    if (threadIdx.x == 0) snz = 0;
-    uint64_t s = 0;
-    bool nz = false, badw = false;
-    for (uint64_t b = b0; b < b1; ++b) {
-        const uint32_t wb = w[b];
-        s += wb;
-        nz |= wb != 0 || a[b] != 0;
-        badw |= wb > 32;
+    uint32_t bad = 0;
+    const uint64_t before = block_sum(widths_part(w, s0, &bad), sbuf);
+    bad = 0;   // widths outside the segment are checked by their own workgroup
+    uint64_t carry = before;
+    for (uint64_t t0 = s0; t0 < s1; t0 += kThreads) {
+        const uint64_t b = t0 + threadIdx.x;
+        const uint32_t v = b < s1 ? w[b] : 0u;
+        bad |= v > 32 ? 1u : 0u;
+        uint64_t ex;
+        const uint64_t tsum = block_exclusive_scan(v, &ex, sbuf);
+        if (b < s1) off[c * nb + b] = (uint32_t)(carry + ex);
+        carry += tsum;
     }
-    if (badw) atomicOr(flags, 2u);
-    __syncthreads();
-    if (nz) snz = 1;
-    uint64_t ex;
-    const uint64_t total = block_exclusive_scan(s, &ex, sbuf);
-    for (uint64_t b = b0; b < b1; ++b) {
-        off[c * nb + b] = (uint32_t)ex;
-        ex += w[b];
+    if (bad) atomicOr(flags, 2u);
+    if (!first) return;   // whole workgroup
+    // first segment: the whole chunk's total (widths from s1 on) and kind
+    uint32_t ignore = 0;
+    const uint64_t rest = block_sum(widths_part(w + s1, nb - s1, &ignore), sbuf);
+    const uint64_t total = carry + rest;   // the same in every thread
+    bool general = total != 0;
+    if (!general) {
+        // no payload: the chunk is ZERO unless an anchor is nonzero
+        if (threadIdx.x == 0) snz = 0;
+        __syncthreads();
+        bool nz = false;
+        for (uint64_t i = threadIdx.x; i < nb; i += kThreads) nz |= a[i] != 0;
+        if (nz) snz = 1;
+        __syncthreads();
+        general = snz != 0;
     }
     if (threadIdx.x == 0) {
-        const bool general = snz != 0;
         kinds[c] = general ? 1u : 0u;
         sizes[c] = general ? 32 + pad8(nb) + pad8(4 * nb) + 8 * total : 32;
     }
@@ -427,8 +494,13 @@ hipError_t launch_scan_chunks(const uint8_t *W, const int32_t *A, uint64_t nb, u
                               uint64_t *sizes, uint32_t *kinds, uint32_t *flags, hipStream_t stream)
 {
     if (n_chunks == 0) return hipSuccess;
-    hipLaunchKernelGGL(scan_chunks_kernel, dim3((unsigned)n_chunks), dim3(kThreads), 0, stream, W, A, nb, off,
-                       sizes, kinds, flags);
+    if (n_chunks > 0x7fffffffull) return hipErrorInvalidValue;
+    // segments of at least 2048 blocks, at most 64 per chunk
+    uint64_t segs = nb / 2048;
+    if (segs < 1) segs = 1;
+    if (segs > 64) segs = 64;
+    hipLaunchKernelGGL(scan_chunks_kernel, dim3((unsigned)n_chunks, (unsigned)segs), dim3(kThreads), 0, stream, W,
+                       A, nb, off, sizes, kinds, flags);
     return hipGetLastError();
 }
 
@@ -454,6 +526,10 @@ hipError_t launch_scan_sizes(const uint64_t *sizes, uint64_t n, uint64_t *offset
     return hipGetLastError();
 }
 
+// One wave per 64 consecutive blocks (lane = block): the lanes write their
+// blocks' widths and anchors side by side, the lane of a chunk's first block
+// writes that chunk's header, then the wave copies the payload of its blocks
+// one block at a time (lanes = the block's plane words). nb is a power of two.
 __global__ __launch_bounds__(kThreads) void assemble_chunks_kernel(int dtype, int log2c, double eb,
                                                                    const uint8_t *W, const int32_t *A,
                                                                    const uint32_t *src_off, const uint64_t *src,
@@ -465,41 +541,51 @@ __global__ __launch_bounds__(kThreads) void assemble_chunks_kernel(int dtype, in
     const uint32_t lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t total_blocks = nb * n_chunks;
+    const int lnb = __builtin_ctzll(nb);
     const uint64_t a_off = 32 + pad8(nb), p_off = a_off + pad8(4 * nb);
-    for (uint64_t gb = (uint64_t)blockIdx.x * NW + wave; gb < total_blocks; gb += (uint64_t)gridDim.x * NW) {
-        const uint64_t c = gb / nb, b = gb - c * nb;
-        uint8_t *o = out + offsets[c];
-        const bool general = kinds[c] != 0;
-        if (b == 0 && lane < 8) {
-            // header as eight 32-bit words
-            uint32_t v = 0;
-            switch (lane) {
-            case 0: v = 0x4356534Du; break;
-            case 1: v = 1u | ((general ? 1u : 0u) << 8) | ((uint32_t)log2c << 16) | ((uint32_t)dtype << 24); break;
-            case 2: v = (uint32_t)(__double_as_longlong(eb) & 0xffffffffull); break;
-            case 3: v = (uint32_t)((unsigned long long)__double_as_longlong(eb) >> 32); break;
-            case 4: v = (uint32_t)(sizes[c] & 0xffffffffull); break;
-            case 5: v = (uint32_t)(sizes[c] >> 32); break;
-            case 6: v = (uint32_t)nb; break;
-            default: v = 0; break;
+    const uint64_t stride = (uint64_t)gridDim.x * NW * 64;
+    for (uint64_t g0 = ((uint64_t)blockIdx.x * NW + wave) * 64; g0 < total_blocks; g0 += stride) {
+        const uint64_t gb = g0 + lane;
+        const bool in = gb < total_blocks;
+        const uint64_t c = in ? gb >> lnb : 0, b = gb & (nb - 1);
+        uint8_t *o = out + (in ? offsets[c] : 0);
+        const bool general = in && kinds[c] != 0;
+        if (in && b == 0) {
+            uint32_t *h = reinterpret_cast<uint32_t *>(o);
+            const uint64_t ebits = (uint64_t)__double_as_longlong(eb);
+            h[0] = 0x4356534Du;
+            h[1] = 1u | ((general ? 1u : 0u) << 8) | ((uint32_t)log2c << 16) | ((uint32_t)dtype << 24);
+            h[2] = (uint32_t)(ebits & 0xffffffffull);
+            h[3] = (uint32_t)(ebits >> 32);
+            h[4] = (uint32_t)(sizes[c] & 0xffffffffull);
+            h[5] = (uint32_t)(sizes[c] >> 32);
+            h[6] = (uint32_t)nb;
+            h[7] = 0u;
+            if (general) {
+                // zero padding after W and after A
+                for (uint64_t i = 32 + nb; i < a_off; ++i) o[i] = 0;
+                for (uint64_t i = a_off + 4 * nb; i < p_off; ++i) o[i] = 0;
             }
-            reinterpret_cast<uint32_t *>(o)[lane] = v;
         }
-        if (!general) continue;
-        if (b == 0) {
-            // zero padding after W and after A
-            for (uint64_t i = 32 + nb + lane; i < a_off; i += 64) o[i] = 0;
-            for (uint64_t i = a_off + 4 * nb + lane; i < p_off; i += 64) o[i] = 0;
-        }
-        const uint32_t w = W[gb];
-        if (lane == 0) {
+        uint32_t w = 0;
+        uint64_t d = 0, so = 0;
+        if (general) {
+            w = W[gb];
             o[32 + b] = (uint8_t)w;
             reinterpret_cast<int32_t *>(o + a_off)[b] = A[gb];
+            d = (uint64_t)(uintptr_t)(reinterpret_cast<uint64_t *>(o) + p_off / 8 + dst_off[gb]);
+            so = src_off ? (uint64_t)src_off[gb] : gb * 32;
         }
-        if (lane < w) {
-            const uint64_t d = p_off / 8 + dst_off[gb] + lane;
-            const uint64_t so = src_off ? (uint64_t)src_off[gb] : gb * 32;
-            reinterpret_cast<uint64_t *>(o)[d] = src[so + lane];
+        uint64_t m = __ballot(w != 0);
+        while (m) {
+            const int j = __builtin_ctzll(m);
+            m &= m - 1;
+            const uint32_t wj = (uint32_t)__builtin_amdgcn_readlane((int)w, j);
+            const uint64_t dj = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(d >> 32), j) << 32) |
+                                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)d, j);
+            const uint64_t sj = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(so >> 32), j) << 32) |
+                                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)so, j);
+            if (lane < wj) reinterpret_cast<uint64_t *>((uintptr_t)dj)[lane] = src[sj + lane];
         }
     }
 }
@@ -510,14 +596,20 @@ hipError_t launch_assemble_chunks(int dtype, int log2c, double eb, const uint8_t
                                   uint64_t n_chunks, uint8_t *out, hipStream_t stream)
 {
     const uint64_t nb = (2ull << log2c) / 64;
-    uint64_t g = (nb * n_chunks + 3) / 4;
-    if (g > 65536) g = 65536;
+    if (log2c < 6 || (nb & (nb - 1)) != 0) return hipErrorInvalidValue;
+    uint64_t g = (nb * n_chunks + kThreads - 1) / kThreads;
+    if (g > 4096) g = 4096;
     if (g == 0) return hipSuccess;
     hipLaunchKernelGGL(assemble_chunks_kernel, dim3((unsigned)g), dim3(kThreads), 0, stream, dtype, log2c, eb, W, A,
                        src_off, src_heap, dst_off, sizes, kinds, offsets, nb, n_chunks, out);
     return hipGetLastError();
 }
 
+
+// Grid: x = chunk, y = segment of the chunk's blocks. Every workgroup checks
+// the header and the widths of the whole chunk (so all of a chunk's
+// workgroups take the same accept/reject decision), sums the widths before
+// its segment, then scans its own segment in tiles of kThreads blocks.
 __global__ __launch_bounds__(kThreads) void parse_chunks_kernel(const uint8_t *base, const uint64_t *offsets,
                                                                 const uint64_t *staged, int log2c, uint64_t nb,
                                                                 uint8_t *W, int32_t *A, uint32_t *OFF,
@@ -526,6 +618,10 @@ __global__ __launch_bounds__(kThreads) void parse_chunks_kernel(const uint8_t *b
     __shared__ uint64_t sbuf[kThreads];
     __shared__ int sbad;
     const uint64_t c = blockIdx.x;
+    const uint64_t seg_len = (nb + gridDim.y - 1) / gridDim.y;
+    const uint64_t s0 = (uint64_t)blockIdx.y * seg_len;
+    if (s0 >= nb) return;   // whole workgroup, before any barrier
+    const uint64_t s1 = s0 + seg_len < nb ? s0 + seg_len : nb;
     const uint8_t *o = base + offsets[c];
     const uint64_t have = staged[c];
     const uint64_t a_off = 32 + pad8(nb), p_off = a_off + pad8(4 * nb);
@@ -545,32 +641,36 @@ __global__ __launch_bounds__(kThreads) void parse_chunks_kernel(const uint8_t *b
     }
     const bool general = !hdr_bad && kind == 1;
     if (threadIdx.x == 0) sbad = hdr_bad ? 1 : 0;
-    const uint64_t per = (nb + kThreads - 1) / kThreads;
-    const uint64_t b0 = threadIdx.x * per, b1 = b0 + per < nb ? b0 + per : nb;
-    uint64_t s = 0;
-    bool wbad = false;
-    for (uint64_t b = b0; b < b1; ++b) {
-        const uint32_t w = general ? o[32 + b] : 0u;
-        wbad |= w > 32;
-        s += w;
-    }
     __syncthreads();
+    const uint8_t *wb = o + 32;
+    uint32_t wbad = 0;
+    uint64_t pre = 0, all = 0;
+    if (general) {
+        pre = widths_part(wb, s0, &wbad);
+        all = pre + widths_part(wb + s0, nb - s0, &wbad);
+    }
     if (wbad) sbad = 1;
-    uint64_t ex;
-    const uint64_t words = block_exclusive_scan(s, &ex, sbuf);
+    const uint64_t words = block_sum(all, sbuf);
+    const uint64_t before = block_sum(pre, sbuf);
     if (threadIdx.x == 0 && general && p_off + 8 * words != total) sbad = 1;
     __syncthreads();
     const bool ok = general && sbad == 0;
-    const uint64_t pay0 = (offsets[c] + p_off) / 8;
-    for (uint64_t b = b0; b < b1; ++b) {
-        const uint64_t gb = c * nb + b;
-        const uint32_t w = ok ? o[32 + b] : 0u;
-        W[gb] = (uint8_t)w;
-        A[gb] = ok ? reinterpret_cast<const int32_t *>(o + a_off)[b] : 0;
-        OFF[gb] = ok ? (uint32_t)(pay0 + ex) : 0u;
-        ex += w;
+    uint64_t carry = (offsets[c] + p_off) / 8 + before;
+    for (uint64_t t0 = s0; t0 < s1; t0 += kThreads) {
+        const uint64_t b = t0 + threadIdx.x;
+        const bool in = b < s1;
+        const uint32_t w = ok && in ? wb[b] : 0u;
+        uint64_t ex;
+        const uint64_t tsum = block_exclusive_scan(w, &ex, sbuf);
+        if (in) {
+            const uint64_t gb = c * nb + b;
+            W[gb] = (uint8_t)w;
+            A[gb] = ok ? reinterpret_cast<const int32_t *>(o + a_off)[b] : 0;
+            OFF[gb] = ok ? (uint32_t)(carry + ex) : 0u;
+        }
+        carry += tsum;
     }
-    if (threadIdx.x == 0 && sbad) atomicOr(flags, 4u);
+    if (threadIdx.x == 0 && blockIdx.y == 0 && sbad) atomicOr(flags, 4u);
 }
 
 hipError_t launch_parse_chunks(const uint8_t *base, const uint64_t *offsets, const uint64_t *staged,
@@ -578,9 +678,14 @@ hipError_t launch_parse_chunks(const uint8_t *base, const uint64_t *offsets, con
                                uint32_t *flags, hipStream_t stream)
 {
     if (n_chunks == 0) return hipSuccess;
+    if (n_chunks > 0x7fffffffull) return hipErrorInvalidValue;
     const uint64_t nb = (2ull << log2c) / 64;
-    hipLaunchKernelGGL(parse_chunks_kernel, dim3((unsigned)n_chunks), dim3(kThreads), 0, stream, base, offsets,
-                       staged, log2c, nb, W, A, OFF, flags);
+    // segments of at least 2048 blocks, at most 64 per chunk
+    uint64_t segs = nb / 2048;
+    if (segs < 1) segs = 1;
+    if (segs > 64) segs = 64;
+    hipLaunchKernelGGL(parse_chunks_kernel, dim3((unsigned)n_chunks, (unsigned)segs), dim3(kThreads), 0, stream, base,
+                       offsets, staged, log2c, nb, W, A, OFF, flags);
     return hipGetLastError();
 }
 
