@@ -96,6 +96,29 @@ def test_rejections():
     assert e.value.code == -6
 
 
+@pytest.mark.parametrize("where", ["first", "middle", "last"])
+def test_rejections_in_every_segment_of_a_large_chunk(where):
+    """A 2^18-amplitude chunk has 8192 blocks, which the decode splits into
+    several segments; a corrupt width anywhere must reject the whole chunk,
+    and an intact copy must still decode bit-exactly afterwards."""
+    from paper_2309_16979_amd import codec_decode, MsvError
+    lc, eb = 18, 1e-5
+    nb = (2 << lc) // 64
+    x = _gauss(lc, 2 ** -14.5, np.complex64, seed=7)
+    blob = oracle.codec_encode(x, lc, eb)
+    assert blob[5] == 1                      # GENERAL chunk
+    b = {"first": 1, "middle": nb // 2 + 3, "last": nb - 2}[where]
+    for new in (lambda w: w + 1 if w < 32 else w - 1, lambda w: 40):
+        bad = bytearray(blob)
+        bad[32 + b] = new(bad[32 + b])
+        log("codec corrupt large chunk", where, bad[32 + b])
+        with pytest.raises(MsvError) as e:
+            codec_decode(bytes(bad), "c64")
+        assert e.value.code == -6
+    got = codec_decode(blob, "c64")
+    assert np.array_equal(got.view(np.uint8), oracle.codec_decode(blob).view(np.uint8))
+
+
 @pytest.mark.parametrize("dtype", [np.complex128, np.complex64])
 @pytest.mark.parametrize("lc,sigma,eb", [(6, 1e-3, 1e-5), (12, 2 ** -14.5, 1e-5), (16, 1e-2, 1e-4)])
 def test_decode_of_oracle_chunks_bit_exact(dtype, lc, sigma, eb):
