@@ -437,7 +437,7 @@ static __device__ __forceinline__ uint64_t widths_part(const uint8_t *w, uint64_
 }
 
 // Grid: x = chunk, y = segment of the chunk's blocks. Each workgroup sums the
-// widths before its segment and scans its segment in tiles of kThreads
+// widths before its segment and scans its segment in tiles of 4 * kThreads
 // blocks; the first one also sums the whole chunk and decides its kind (all
 // widths and anchors zero: ZERO).
 __global__ __launch_bounds__(kThreads) void scan_chunks_kernel(const uint8_t *W, const int32_t *A, uint64_t nb,
@@ -458,13 +458,24 @@ __global__ __launch_bounds__(kThreads) void scan_chunks_kernel(const uint8_t *W,
     const uint64_t before = block_sum(widths_part(w, s0, &bad), sbuf);
     bad = 0;   // widths outside the segment are checked by their own workgroup
     uint64_t carry = before;
-    for (uint64_t t0 = s0; t0 < s1; t0 += kThreads) {
-        const uint64_t b = t0 + threadIdx.x;
-        const uint32_t v = b < s1 ? w[b] : 0u;
-        bad |= v > 32 ? 1u : 0u;
+    // tiles of 4 * kThreads blocks, four consecutive blocks per thread
+    for (uint64_t t0 = s0; t0 < s1; t0 += 4 * kThreads) {
+        const uint64_t b = t0 + 4 * (uint64_t)threadIdx.x;
+        uint32_t v[4], sum = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = b + k < s1 ? w[b + k] : 0u;
+            bad |= v[k] > 32 ? 1u : 0u;
+            sum += v[k];
+        }
         uint64_t ex;
-        const uint64_t tsum = block_exclusive_scan(v, &ex, sbuf);
-        if (b < s1) off[c * nb + b] = (uint32_t)(carry + ex);
+        const uint64_t tsum = block_exclusive_scan(sum, &ex, sbuf);
+        uint64_t run = carry + ex;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (b + k < s1) off[c * nb + b + k] = (uint32_t)run;
+            run += v[k];
+        }
         carry += tsum;
     }
     if (bad) atomicOr(flags, 2u);
@@ -609,7 +620,7 @@ hipError_t launch_assemble_chunks(int dtype, int log2c, double eb, const uint8_t
 // Grid: x = chunk, y = segment of the chunk's blocks. Every workgroup checks
 // the header and the widths of the whole chunk (so all of a chunk's
 // workgroups take the same accept/reject decision), sums the widths before
-// its segment, then scans its own segment in tiles of kThreads blocks.
+// its segment, then scans its own segment in tiles of 4 * kThreads blocks.
 __global__ __launch_bounds__(kThreads) void parse_chunks_kernel(const uint8_t *base, const uint64_t *offsets,
                                                                 const uint64_t *staged, int log2c, uint64_t nb,
                                                                 uint8_t *W, int32_t *A, uint32_t *OFF,
@@ -656,17 +667,27 @@ __global__ __launch_bounds__(kThreads) void parse_chunks_kernel(const uint8_t *b
     __syncthreads();
     const bool ok = general && sbad == 0;
     uint64_t carry = (offsets[c] + p_off) / 8 + before;
-    for (uint64_t t0 = s0; t0 < s1; t0 += kThreads) {
-        const uint64_t b = t0 + threadIdx.x;
-        const bool in = b < s1;
-        const uint32_t w = ok && in ? wb[b] : 0u;
+    // tiles of 4 * kThreads blocks, four consecutive blocks per thread
+    for (uint64_t t0 = s0; t0 < s1; t0 += 4 * kThreads) {
+        const uint64_t b = t0 + 4 * (uint64_t)threadIdx.x;
+        uint32_t w[4], sum = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            w[k] = ok && b + k < s1 ? wb[b + k] : 0u;
+            sum += w[k];
+        }
         uint64_t ex;
-        const uint64_t tsum = block_exclusive_scan(w, &ex, sbuf);
-        if (in) {
-            const uint64_t gb = c * nb + b;
-            W[gb] = (uint8_t)w;
-            A[gb] = ok ? reinterpret_cast<const int32_t *>(o + a_off)[b] : 0;
-            OFF[gb] = ok ? (uint32_t)(carry + ex) : 0u;
+        const uint64_t tsum = block_exclusive_scan(sum, &ex, sbuf);
+        uint64_t run = carry + ex;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (b + k < s1) {
+                const uint64_t gb = c * nb + b + k;
+                W[gb] = (uint8_t)w[k];
+                A[gb] = ok ? reinterpret_cast<const int32_t *>(o + a_off)[b + k] : 0;
+                OFF[gb] = ok ? (uint32_t)run : 0u;
+            }
+            run += w[k];
         }
         carry += tsum;
     }
