@@ -135,7 +135,9 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, Bloc
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t nab = a.amp_count >> 6, first = a.amp_begin >> 6;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    // four named accumulators (an array here ends up in scratch memory,
+    // indexed at run time by the reduction kind)
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
     // Z-strings (up to 64 terms): per block G (64 amplitudes, lane = index
     // bits 0..5) the expectation is sum_t c_t (-1)^popcount(G & h_t) P^(l_t),
     // with l_t / h_t the low 6 / high bits of mask m_t and P^ the 64-point
@@ -159,9 +161,9 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, Bloc
         xi *= a.scale;
         const uint64_t i = (G << 6) | (uint64_t)lane;
         const double p = xr * xr + xi * xi;
-        acc[0] += p;
+        acc0 += p;
         if (a.kind == RED_PROB1) {
-            if ((i >> a.qubit) & 1ull) acc[1] += p;
+            acc1 += ((i >> a.qubit) & 1ull) ? p : 0.0;
         } else if (a.kind == RED_EXPZ) {
             if (fast) {
                 double P = p;
@@ -171,25 +173,25 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, Bloc
                     P = (lane & d) ? o - P : P + o;
                 }
                 const double ph = __shfl(P, lsrc, 64);
-                acc[1] += ((__popcll(G & mhi) & 1) ? -ct : ct) * ph;
+                acc1 += ((__popcll(G & mhi) & 1) ? -ct : ct) * ph;
             } else {
                 double v = 0.0;
                 for (int t = 0; t < a.n_terms; ++t)
                     v += (__popcll(i & a.masks[t]) & 1) ? -a.coeffs[t] : a.coeffs[t];
-                acc[1] += p * v;
+                acc1 += p * v;
             }
         } else if (a.kind == RED_OVERLAP) {
             const uint64_t r = i - a.amp_begin;
             const double rr = a.ref[2 * r], ri = a.ref[2 * r + 1];
-            acc[1] += rr * xr + ri * xi;   // Re(conj(ref) psi)
-            acc[2] += rr * xi - ri * xr;   // Im(conj(ref) psi)
-            acc[3] += rr * rr + ri * ri;
+            acc1 += rr * xr + ri * xi;   // Re(conj(ref) psi)
+            acc2 += rr * xi - ri * xr;   // Im(conj(ref) psi)
+            acc3 += rr * rr + ri * ri;
         }
     });
+    const double sums[4] = {wave_sum_f64(acc0), wave_sum_f64(acc1), wave_sum_f64(acc2), wave_sum_f64(acc3)};
+    if (lane == 0) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const double s = wave_sum_f64(acc[j]);
-        if (lane == 0) sacc[j][wave] = s;
+        for (int j = 0; j < 4; ++j) sacc[j][wave] = sums[j];
     }
     __syncthreads();
     if (threadIdx.x < 4) {
