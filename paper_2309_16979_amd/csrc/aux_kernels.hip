@@ -154,6 +154,10 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, Bloc
         mhi = a.masks[lane] >> 6;
         lsrc = (int)(a.masks[lane] & 63u);
     }
+    // butterfly stage k: lanes with bit k set take o - P, the others o + P;
+    // as fma(+-1, P, o) this is one rounding, the same as the add it replaces
+    const double s0 = (lane & 1) ? -1.0 : 1.0, s1 = (lane & 2) ? -1.0 : 1.0, s2 = (lane & 4) ? -1.0 : 1.0,
+                 s3 = (lane & 8) ? -1.0 : 1.0, s4 = (lane & 16) ? -1.0 : 1.0, s5 = (lane & 32) ? -1.0 : 1.0;
     __shared__ uint64_t stage[NW * 128];
     for_amp_blocks<T, COMP>(amps, st, step, first, nab, wave, lane, stage + 128 * wave,
                             [&](uint64_t G, double xr, double xi) {
@@ -167,11 +171,12 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, Bloc
         } else if (a.kind == RED_EXPZ) {
             if (fast) {
                 double P = p;
-#pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    const double o = __shfl_xor(P, d, 64);
-                    P = (lane & d) ? o - P : P + o;
-                }
+                P = fma(s0, P, __shfl_xor(P, 1, 64));
+                P = fma(s1, P, __shfl_xor(P, 2, 64));
+                P = fma(s2, P, __shfl_xor(P, 4, 64));
+                P = fma(s3, P, __shfl_xor(P, 8, 64));
+                P = fma(s4, P, __shfl_xor(P, 16, 64));
+                P = fma(s5, P, __shfl_xor(P, 32, 64));
                 const double ph = __shfl(P, lsrc, 64);
                 acc1 += ((__popcll(G & mhi) & 1) ? -ct : ct) * ph;
             } else {
