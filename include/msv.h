@@ -221,6 +221,13 @@ int msv_get_amplitudes(msv_sim *sim, uint64_t first, uint64_t count, void *host_
  * is zero (f_raw is still written). */
 int msv_fidelity(msv_sim *sim, const double *ref_c128, double *f_raw, double *f_norm);
 int msv_get_stats(msv_sim *sim, msv_stats *out);
+/* Per-pass statistics of the last msv_apply (row a7 of the hot path: FP64 norm
+ * and error-bound checks kept on the GPU): 3 doubles per pass, in pass order,
+ * {sum |x|^2 of the pass output before its encode, max |x - x'| of its encode,
+ * payload words written}. With option "renormalize" each pass's input was
+ * scaled by 1/sqrt of the previous pass's first entry. *n_passes receives the
+ * count; out may be NULL to query it, else cap >= 3 * count (MSV_E_ARG). */
+int msv_get_pass_stats(msv_sim *sim, double *out, size_t cap, size_t *n_passes);
 /* Canonical compressed bytes of one chunk (format "MSVC" v1, as produced by
  * msv_codec_encode). *out_bytes receives the size; cap may be 0 to query. */
 int msv_export_chunk(msv_sim *sim, uint64_t chunk, void *host_out, size_t cap,

@@ -59,7 +59,7 @@ EXPORTS = (
     "msv_set_stream", "msv_init_basis", "msv_init_state", "msv_apply", "msv_prob_one",
     "msv_expect_z", "msv_get_amplitudes", "msv_fidelity", "msv_get_stats", "msv_export_chunk",
     "msv_codec_encode", "msv_codec_decode", "msv_codec_bound", "msv_adjoint", "msv_batch_run",
-    "msv_batch_adjoint", "msv_plan_export",
+    "msv_batch_adjoint", "msv_plan_export", "msv_get_pass_stats",
 )
 
 _lib = None
@@ -108,6 +108,7 @@ def load():
         "msv_get_amplitudes": ([P, C.c_uint64, C.c_uint64, P], C.c_int),
         "msv_fidelity": ([P, P, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
         "msv_get_stats": ([P, C.POINTER(Stats)], C.c_int),
+        "msv_get_pass_stats": ([P, P, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
         "msv_export_chunk": ([P, C.c_uint64, P, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
         "msv_codec_encode": ([C.c_int, C.c_int, C.c_double, P, P, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
         "msv_codec_decode": ([C.c_int, P, C.c_size_t, P], C.c_int),

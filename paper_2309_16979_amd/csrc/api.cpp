@@ -234,15 +234,12 @@ int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOpt
         b.ops = (const OpDesc *)s->ws.ops.p;
         b.pool = s->ws.pool.p;
         const bool c = s->compressed();
-        if (!c && p == 0 && s->scale != 1.0) {
-            // plain state: a pending scale is applied by a no-op pass first
-        }
         if (s->time_passes) HIPCHK(s, hipEventRecord(ev[2 * p], stream));
         HIPCHK(s, launch_pass(s->is_double(), c, c, geoms[p], b, stream));
         if (s->time_passes) HIPCHK(s, hipEventRecord(ev[2 * p + 1], stream));
+        // the statistics kernel indexes part by the absolute offsets offs[p], offs[p + 1]
         if (s->renorm)
-            HIPCHK(s, launch_pass_stats(part + 3 * offs[p], (const uint64_t *)s->ws.pass_off.p + p, 1,
-                                        pstats + 3 * p, stream));
+            HIPCHK(s, launch_pass_stats(part, (const uint64_t *)s->ws.pass_off.p + p, 1, pstats + 3 * p, stream));
         if (c) s->cur ^= 1;
         s->stats.kernel_launches += s->renorm ? 2 : 1;
     }
@@ -255,6 +252,7 @@ int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOpt
     HIPCHK(s, hipMemcpyAsync(hflags, s->ws.flags.p, 4, hipMemcpyDeviceToHost, stream));
     HIPCHK(s, hipStreamSynchronize(stream));
     if (per_pass) per_pass->assign(hout, hout + 3 * n_passes);
+    s->pass_log.assign(hout, hout + 3 * n_passes);
     s->stats.t_pass = 0.0;
     for (size_t p = 0; p < ev.size() / 2; ++p) {
         float ms = 0.f;
@@ -776,7 +774,7 @@ int msv_get_amplitudes(msv_sim *s, uint64_t first, uint64_t count, void *host_ou
     if (!count) return MSV_OK;
     hipStream_t stream = s->stream();
     const size_t e = s->elt();
-    if (!s->compressed() && s->store == MSV_STORE_DEVICE && s->scale == 1.0) {
+    if (!s->compressed() && s->scale == 1.0) {
         HIPCHK(s, hipMemcpyAsync(host_out, (uint8_t *)s->amps.p + e * first, e * count, hipMemcpyDeviceToHost, stream));
         HIPCHK(s, hipStreamSynchronize(stream));
         return MSV_OK;
@@ -790,11 +788,11 @@ int msv_get_amplitudes(msv_sim *s, uint64_t first, uint64_t count, void *host_ou
         const uint64_t cnt = std::min<uint64_t>(piece, a1 - b);
         if (s->store == MSV_STORE_HOST_PINNED) {
             if ((st = host_store_decode_range(s, b, cnt, s->ws.tmp2.p))) return st;
-        } else if (s->compressed()) {
-            HIPCHK(s, launch_decode_range(s->is_double(), s->st[s->cur].view(), s->step(), s->scale, b, cnt,
-                                          s->ws.tmp2.p, stream));
         } else {
-            return fail(s, MSV_E_UNSUPPORTED, "scaled plain state read-out");
+            // compressed blocks, or plain amplitudes with a pending renormalisation factor
+            HIPCHK(s, launch_decode_range(s->is_double(), s->compressed(), s->amps.p, s->st[s->cur].view(),
+                                          s->compressed() ? s->step() : 0.0, s->scale, b, cnt, s->ws.tmp2.p,
+                                          stream));
         }
         const uint64_t lo = std::max(b, first), hi = std::min(b + cnt, first + count);
         HIPCHK(s, hipMemcpyAsync((uint8_t *)host_out + e * (lo - first), (uint8_t *)s->ws.tmp2.p + e * (lo - b),
@@ -879,6 +877,18 @@ int msv_get_stats(msv_sim *s, msv_stats *out)
         r.ratio = 1.0;
     }
     *out = r;
+    return MSV_OK;
+}
+
+int msv_get_pass_stats(msv_sim *s, double *out, size_t cap, size_t *n_passes)
+{
+    GUARD(s);
+    if (!n_passes) return fail(s, MSV_E_ARG, "null output");
+    const size_t np = s->pass_log.size() / 3;
+    *n_passes = np;
+    if (!out) return MSV_OK;
+    if (cap < 3 * np) return fail(s, MSV_E_ARG, "buffer holds %zu doubles, %zu needed", cap, 3 * np);
+    std::copy(s->pass_log.begin(), s->pass_log.end(), out);
     return MSV_OK;
 }
 

@@ -291,16 +291,16 @@ hipError_t launch_pass_stats(const double *part, const uint64_t *pass_offsets, i
 
 // ------------------------------------------------------------ range decode
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void decode_range_kernel(BlockStore st, double step, double scale,
-                                                                uint64_t first, uint64_t nab, void *out)
+template <typename T, bool COMP>
+__global__ __launch_bounds__(kThreads) void decode_range_kernel(const void *amps, BlockStore st, double step,
+                                                                double scale, uint64_t first, uint64_t nab, void *out)
 {
     using V2 = typename Vec2<T>::V;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     constexpr int NW = kThreads / 64;
     __shared__ uint64_t stage[NW * 128];
-    for_amp_blocks<T, true>(nullptr, st, step, first, nab, wave, lane, stage + 128 * wave,
+    for_amp_blocks<T, COMP>(amps, st, step, first, nab, wave, lane, stage + 128 * wave,
                             [&](uint64_t G, double xr, double xi) {
         V2 v;
         v.x = (T)xr;
@@ -310,19 +310,26 @@ __global__ __launch_bounds__(kThreads) void decode_range_kernel(BlockStore st, d
     });
 }
 
-hipError_t launch_decode_range(bool is_double, BlockStore st, double step, double scale, uint64_t amp_begin,
-                               uint64_t amp_count, void *out, hipStream_t stream)
+hipError_t launch_decode_range(bool is_double, bool compressed, const void *amps, BlockStore st, double step,
+                               double scale, uint64_t amp_begin, uint64_t amp_count, void *out, hipStream_t stream)
 {
     const uint64_t nab = amp_count >> 6;
     uint64_t g = (nab + 3) / 4;
     if (g > 65536) g = 65536;
     if (g == 0) return hipSuccess;
-    if (is_double)
-        hipLaunchKernelGGL(decode_range_kernel<double>, dim3((unsigned)g), dim3(kThreads), 0, stream, st, step,
-                           scale, amp_begin >> 6, nab, out);
+    const dim3 grid((unsigned)g), block(kThreads);
+    if (is_double && compressed)
+        hipLaunchKernelGGL((decode_range_kernel<double, true>), grid, block, 0, stream, amps, st, step, scale,
+                           amp_begin >> 6, nab, out);
+    else if (is_double)
+        hipLaunchKernelGGL((decode_range_kernel<double, false>), grid, block, 0, stream, amps, st, step, scale,
+                           amp_begin >> 6, nab, out);
+    else if (compressed)
+        hipLaunchKernelGGL((decode_range_kernel<float, true>), grid, block, 0, stream, amps, st, step, scale,
+                           amp_begin >> 6, nab, out);
     else
-        hipLaunchKernelGGL(decode_range_kernel<float>, dim3((unsigned)g), dim3(kThreads), 0, stream, st, step,
-                           scale, amp_begin >> 6, nab, out);
+        hipLaunchKernelGGL((decode_range_kernel<float, false>), grid, block, 0, stream, amps, st, step, scale,
+                           amp_begin >> 6, nab, out);
     return hipGetLastError();
 }
 

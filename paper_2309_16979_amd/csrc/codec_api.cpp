@@ -126,7 +126,7 @@ int msv_codec_decode(int dtype, const void *host_in, size_t in_bytes, void *host
     CHK(hipMemsetAsync(flags, 0, 8, s));
     CHK(launch_parse_chunks(blob, meta, meta + 1, 1, log2c, W, A, OFF, flags, s));
     BlockStore bs{W, A, OFF, (uint64_t *)blob, nullptr, 0};
-    CHK(launch_decode_range(dbl, bs, 2.0 * eb, 1.0, 0, C, out, s));
+    CHK(launch_decode_range(dbl, true, nullptr, bs, 2.0 * eb, 1.0, 0, C, out, s));
     uint32_t hf = 0;
     CHK(hipMemcpyAsync(&hf, flags, 4, hipMemcpyDeviceToHost, s));
     CHK(hipStreamSynchronize(s));

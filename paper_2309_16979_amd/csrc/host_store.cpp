@@ -469,7 +469,9 @@ int apply_host_store(msv_sim *s, const std::vector<Prim> &prims, size_t n_gates)
             pb.inv_step = s->inv_step();
             pb.step = s->step();
             pb.scale = p == 0 ? s->scale : 1.0;
-            pb.scale_src = nullptr;
+            // renormalisation: 1 / sqrt(norm2 of the previous pass), from its
+            // statistics kernel (queued earlier on this stream)
+            pb.scale_src = (s->renorm && p > 0) ? (const double *)s->ws.pass_stats.p + 3 * (p - 1) : nullptr;
             pb.part = (double *)h.part.p + 3 * g.tile_begin;
             pb.flags = v.flags;
             pb.check_err = s->check_bound;
@@ -516,6 +518,7 @@ int apply_host_store(msv_sim *s, const std::vector<Prim> &prims, size_t n_gates)
     if ((st = read_flags(s, &f))) return st;
     s->stats.passes = geoms.size();
     s->stats.fused_ops = ops.size();
+    s->pass_log.assign(hs.begin(), hs.begin() + 3 * geoms.size());
     s->stats.h2d_bytes = h2d_bytes;
     s->stats.d2h_bytes = d2h_bytes;
     s->stats.t_h2d = t_h2d;
@@ -582,7 +585,7 @@ int host_store_decode_range(msv_sim *s, uint64_t first, uint64_t count, void *de
         const uint64_t c1 = std::min(((first + count - 1) >> s->log2c) + 1, c0 + K);
         if ((st = stage_range(s, c0, c1 - c0))) return st;
         const uint64_t hi = std::min(first + count, c1 * C);
-        HIPCHK(s, launch_decode_range(s->is_double(), staged_view(s), s->step(), s->scale, a, hi - a,
+        HIPCHK(s, launch_decode_range(s->is_double(), true, nullptr, staged_view(s), s->step(), s->scale, a, hi - a,
                                       (uint8_t *)dev_out + s->elt() * (a - first), s->stream()));
         HIPCHK(s, hipStreamSynchronize(s->stream()));
         a = hi;

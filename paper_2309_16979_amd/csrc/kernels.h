@@ -106,9 +106,10 @@ hipError_t launch_reduce_final(const double *partials, int n_groups, double *out
 hipError_t launch_pass_stats(const double *part, const uint64_t *pass_offsets, int n_passes,
                              double *out, hipStream_t stream);
 
-// Decode amplitudes [amp_begin, amp_begin + amp_count) (multiples of 64) into out.
-hipError_t launch_decode_range(bool is_double, BlockStore st, double step, double scale,
-                               uint64_t amp_begin, uint64_t amp_count, void *out,
+// Decode amplitudes [amp_begin, amp_begin + amp_count) (multiples of 64) into
+// out, times scale: from the block store (compressed) or the plain amplitudes.
+hipError_t launch_decode_range(bool is_double, bool compressed, const void *amps, BlockStore st, double step,
+                               double scale, uint64_t amp_begin, uint64_t amp_count, void *out,
                                hipStream_t stream);
 
 // ---- canonical chunk format (codec API, export, host store) ----------------

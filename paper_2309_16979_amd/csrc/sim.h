@@ -109,6 +109,7 @@ struct msv_sim {
     msv::Workspace ws;
     double scale = 1.0;        // pending renormalisation factor, applied at decode
     msv_stats stats{};
+    std::vector<double> pass_log;   // last apply: per pass (norm2, max error, payload words)
     double max_err_all = 0.0;
     uint64_t compressed_words = 0;  // payload words of the current state
 

@@ -197,6 +197,15 @@ class Simulator:
         self._chk(self._L.msv_get_stats(self.h, C.byref(st)))
         return st.as_dict()
 
+    def pass_stats(self) -> np.ndarray:
+        """Per-pass (norm2 before encode, max |x - x'|, payload words) of the
+        last apply, shape (passes, 3)."""
+        n = C.c_size_t(0)
+        self._chk(self._L.msv_get_pass_stats(self.h, None, 0, C.byref(n)))
+        out = np.zeros(max(1, 3 * n.value), dtype=np.float64)
+        self._chk(self._L.msv_get_pass_stats(self.h, out.ctypes.data, out.size, C.byref(n)))
+        return out[: 3 * n.value].reshape(n.value, 3)
+
     def adjoint(self, gates: Sequence, params, masks, coeffs, checkpoints: Sequence[int] = ()):
         """Expectation of sum_k c_k Z(m_k) after `gates` (parameterised gates
         take theta = params[gate.param]) from the current state, and its

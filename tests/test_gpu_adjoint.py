@@ -88,10 +88,48 @@ def test_adjoint_all_parameterised_kinds():
     assert np.max(np.abs(g - ref5)) <= 1e-8
 
 
-def test_adjoint_ansatz_n22_against_finite_differences():
+def _sampled_params(n, layers, seed, per_layer_kind=3):
+    """Per layer, `per_layer_kind` RY and as many RZ parameters on seeded
+    random qubits (6 layers x 2 kinds x 3 = 36 parameters at n = 22)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for layer in range(layers):
+        for q in rng.choice(n, size=per_layer_kind, replace=False):
+            out.append(2 * n * layer + 2 * int(q))
+        for q in rng.choice(n, size=per_layer_kind, replace=False):
+            out.append(2 * n * layer + 2 * int(q) + 1)
+    return sorted(out)
+
+
+def _shift_gradient_sampled(n, gates, params, masks, coeffs, which):
+    """Oracle parameter-shift gradient (exact for RY, RZ) of the parameters in
+    `which`, each feeding one gate: the state before that gate is simulated
+    once (incrementally over the sorted parameters), then the rest of the
+    circuit twice, with the angle shifted by +-pi/2."""
+    bound = oracle.bind_params(gates, params)
+    at = {g.param: i for i, g in enumerate(gates) if g.param >= 0}
+    psi, pos, out = oracle.basis(n, 0), 0, {}
+    for p in sorted(which, key=lambda p: at[p]):
+        gi = at[p]
+        psi = oracle.simulate(n, bound[pos:gi], psi)
+        pos = gi
+        vals = []
+        for sh in (math.pi / 2, -math.pi / 2):
+            pp = params.copy()
+            pp[p] += sh
+            tail = oracle.bind_params(gates[gi:], pp)
+            vals.append(oracle.expect_z(n, oracle.simulate(n, tail, psi), masks, coeffs))
+        out[p] = 0.5 * (vals[0] - vals[1])
+    return out
+
+
+@pytest.mark.timeout(900)
+def test_adjoint_ansatz_n22_against_parameter_shift():
     """The n=22 ansatz (6 layers, checkpoints every 2 layers, complex64):
-    gradient of sampled parameters against central differences (h = 1e-3,
-    FP64 oracle); the compressed run (eb = 1e-4) is reported against it."""
+    36 sampled parameters, RY and RZ in every layer, against the oracle's
+    parameter-shift gradient (exact for these gates) at 1e-4, and 4 of them
+    against central differences (h = 1e-3, FP64). The compressed run
+    (eb = 1e-4) is reported against it."""
     n, layers = 22, 6
     gates = ansatz(n, layers)
     params = ansatz_params(n, layers, seed=0)[0]
@@ -105,15 +143,24 @@ def test_adjoint_ansatz_n22_against_finite_differences():
     with _sim(n, "c64", 1e-4, chunk_qubits=16) as s:
         s.init_basis(0)
         ev_c, g_c = s.adjoint(gates, params, masks, coeffs, ck)
-    sample = [0, 45, 131, 263]
-    h = 1e-3
+    sample = _sampled_params(n, layers, seed=22)
+    assert len(sample) >= 32
+    assert {p % 2 for p in sample} == {0, 1} and {p // (2 * n) for p in sample} == set(range(layers))
+    ps = _shift_gradient_sampled(n, gates, params, masks, coeffs, sample)
+    worst = 0.0
     for i in sample:
+        worst = max(worst, abs(g[i] - ps[i]))
+        assert abs(g[i] - ps[i]) <= 1e-4, (i, g[i], ps[i])
+    assert ev == pytest.approx(oracle.energy(n, gates, params, masks, coeffs), abs=1e-4)
+    h = 1e-3
+    for i in sample[:: len(sample) // 4][:4]:
         a = params.copy(); a[i] += h
         b = params.copy(); b[i] -= h
         fd = (oracle.energy(n, gates, a, masks, coeffs) - oracle.energy(n, gates, b, masks, coeffs)) / (2 * h)
-        assert abs(g[i] - fd) <= 1e-3, (i, g[i], fd)
-        print("param", i, "fd", fd, "adjoint", g[i], "compressed", g_c[i])
-    print("expval", ev, "compressed", ev_c, "max |g - g_c|", float(np.max(np.abs(g - g_c))))
+        assert abs(g[i] - fd) <= 1e-4, (i, g[i], fd)
+    print("n22 adjoint: %d parameters, max |g - g_shift| %.3g; compressed eb=1e-4: max |g_c - g_shift| %.3g"
+          % (len(sample), worst, max(abs(g_c[i] - ps[i]) for i in sample)))
+    print("expval", ev, "compressed", ev_c)
     assert np.all(np.isfinite(g_c))
 
 

@@ -169,3 +169,34 @@ def test_wide_blocks_through_pass_kernels(eb, amp):
     assert np.array_equal(got.view(np.uint8), ref.view(np.uint8))
     widths = np.frombuffer(chunk, dtype=np.uint8)[32:32 + 2 * (1 << n) // 64]
     assert widths.max() >= (30 if eb < 1e-9 else 20)
+
+
+@pytest.mark.timeout(600)
+def test_host_store_crossing_circuit_against_oracle():
+    """The host-store workload's circuit shape at n = 24: chunks of 2^18
+    amplitudes in pinned host memory, 30 % two-qubit gates on chunk-crossing
+    qubits, eb = 1e-5. Checked against the FP64 oracle: every pass within the
+    codec bound, F_norm within the quantisation budget 1 - 1.5 P (2/3) 2^n eb^2,
+    and P(q = 1) of a crossing qubit within the bound's effect on it."""
+    from workloads import crossing_circuit
+    n, lc, eb = 24, 18, 1e-5
+    gates = crossing_circuit(n, 20, lc, seed=2)
+    ref = oracle.simulate(n, gates, 0)
+    log("host crossing", n, lc, eb, len(gates))
+    with _sim(n, "c64", eb, chunk_qubits=lc, store="host") as s:
+        s.init_basis(0)
+        s.apply(gates)
+        st = s.stats()
+        ps = s.pass_stats()
+        fr, fn = s.fidelity(ref)
+        p1 = s.prob_one(n - 1)
+    P = st["passes"]
+    assert P >= 2 and st["bound_violations"] == 0 and np.all(ps[:, 1] <= st["err_bound"])
+    assert st["h2d_bytes"] > 0 and st["d2h_bytes"] > 0
+    budget = 1.0 - 1.5 * P * (2.0 / 3.0) * (1 << n) * eb * eb
+    print("host crossing n=24: passes %d, F_raw %.6f, F_norm %.6f (budget %.4f), ratio %.2f"
+          % (P, fr, fn, budget, st["ratio"]))
+    assert fn >= budget
+    # |p1 - p1_ref| <= 2 ||e|| + ||e||^2 with ||e|| <= P eb' sqrt(2^(n+1))
+    e = P * st["err_bound"] * math.sqrt(2.0 * (1 << n))
+    assert abs(p1 - oracle.prob_one(ref, n - 1)) <= 2 * e + e * e

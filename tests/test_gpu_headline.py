@@ -1,0 +1,83 @@
+"""The benchmark's own circuit against the FP64 oracle at full size: n = 28,
+QFT of a seeded random basis state followed by 100 random one- and two-qubit
+gates (520 gates), complex64, chunks of 2^20 amplitudes.
+
+* Uncompressed complex64 GPU run: every one of the 2^28 amplitudes within
+  1e-5 of the oracle, and the relative 2-norm error within 1e-5.
+* Compressed run at eb = 1e-5 (device store, the benchmark's settings): every
+  pass within the codec bound, and F_norm against the oracle reported and held
+  to the statistical quantisation budget 1 - 1.5 P (2/3) 2^n eb^2 (P passes).
+
+The oracle needs a 4 GiB complex128 state and about a minute on 16 host
+threads; it runs once for the module."""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.gpu_util import ensure_built, log
+from workloads import qft_plus_random
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+
+N = 28
+SEED = 0
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    ensure_built()
+
+
+@pytest.fixture(scope="module")
+def case():
+    x, gates = qft_plus_random(N, 100, SEED)
+    log("headline oracle n=28 (4 GiB, ~1 min)")
+    ref = oracle.simulate(N, gates, x)
+    return x, gates, ref
+
+
+def _sim(**kw):
+    from paper_2309_16979_amd import Simulator
+    return Simulator(N, dtype="c64", chunk_qubits=20, k_max=2, **kw)
+
+
+def test_headline_uncompressed_c64_elementwise(case):
+    x, gates, ref = case
+    log("headline c64 eb=0")
+    piece = 1 << 24
+    worst, d2, r2 = 0.0, 0.0, 0.0
+    with _sim(eb=0.0) as s:
+        s.init_basis(x)
+        s.apply(gates)
+        for a in range(0, 1 << N, piece):
+            got = s.amplitudes(a, piece).astype(np.complex128)
+            d = got - ref[a:a + piece]
+            worst = max(worst, float(np.max(np.abs(d))))
+            d2 += float(np.vdot(d, d).real)
+            r2 += float(np.vdot(ref[a:a + piece], ref[a:a + piece]).real)
+    rel = math.sqrt(d2 / r2)
+    print("headline c64 uncompressed: max|d| %.3g, relative L2 %.3g" % (worst, rel))
+    assert worst <= 1e-5
+    assert rel <= 1e-5
+
+
+def test_headline_compressed_fidelity(case):
+    x, gates, ref = case
+    eb = 1e-5
+    log("headline c64 eb=1e-5")
+    with _sim(eb=eb) as s:
+        s.init_basis(x)
+        s.apply(gates)
+        st = s.stats()
+        ps = s.pass_stats()
+        fr, fn = s.fidelity(ref)
+    P = st["passes"]
+    assert st["bound_violations"] == 0 and st["max_err_all"] <= st["err_bound"]
+    assert np.all(ps[:, 1] <= st["err_bound"])
+    budget = 1.0 - 1.5 * P * (2.0 / 3.0) * (1 << N) * eb * eb
+    print("headline c64 eb=1e-5: passes %d, F_raw %.6f, F_norm %.6f (budget %.4f), ratio %.2f"
+          % (P, fr, fn, budget, st["ratio"]))
+    assert fn >= budget
