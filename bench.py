@@ -3,31 +3,33 @@
 Workload (default): n = 28 qubits, complex64 state held as compressed chunks of
 2^20 amplitudes in HBM, error bound 1e-5 per component; circuit = QFT on a
 seeded random basis state followed by 100 random one/two-qubit gates (520
-gates). One step = init the basis state + apply the whole circuit as streamed
-decode -> fused gates -> encode passes + the ZZ-chain expectation (an FP64
-reduction over the decoded state). Metric: amplitude-gate updates per second
-including the codec = steps * gates * 2^n / time.
+gates). One step = init the basis state + apply the whole circuit (planning
+of passes and fusion included: the plan is not reused between steps) as
+streamed decode -> fused gates -> encode passes + the ZZ-chain expectation (an
+FP64 reduction over the decoded state). Metric: amplitude-gate updates per
+second including the codec = steps * gates * 2^n / time.
 
-Prints one JSON line with the driver's fields plus "roofline" (pass kernel,
-durations from HIP events around every pass launch on the stream it runs on)
-and "cpu_baseline" (the FP64 oracle on a bounded sample of the same circuit).
+Prints one JSON line with the driver's fields plus "roofline" (the pass
+kernel: algorithmic bytes per launch over its average launch duration, from
+HIP events around every pass launch on the stream it runs on, against the HBM
+bandwidth a copy kernel measures on the same device), "denominators" (the
+measured HBM, host-link and matrix-core peaks) and "cpu_baseline" (the FP64
+oracle on a bounded sample of the same circuit).
 
-The compressed pass is bound by vector-ALU work (codec bit planes, prefix
-sums, FP64 quantisation, gate arithmetic), not by HBM. Its roofline is the
-vector-ALU issue rate: each of the 1024 SIMDs issues one wave64 instruction
-per four cycles, or two when both are FP32 add/mul/fma (FP64 ops, conversions,
-compares and cross-lane ops issue alone). The library counts the algorithmic
-lane operations of each pass (gate arithmetic per amplitude, W + 15 per codec
-value and direction) in single-issue equivalents (FP32 gate ops count 1/2);
-the peak is 256 CUs x 64 lanes x 2.4 GHz = 39.3 T of them per second, which
-is the FP64 vector rate (78.6 TFLOP/s) and half the FP32 rate (157.3 TFLOP/s).
-The HBM view (algorithmic bytes / time, and counter-measured traffic) is
-reported beside it.
+The compressed pass moves few bytes (about 10x fewer than the plain state),
+so its HBM fraction is small: the pass is bound by vector-ALU issue (codec bit
+planes, prefix sums, FP64 quantisation, gate arithmetic). That view is
+reported beside the HBM one in roofline.alu: the library counts the
+algorithmic lane operations of each pass in single-issue equivalents (FP32
+gate arithmetic and 32-bit bit-plane ops count 1/2, since two of them issue
+per slot); the peak is 256 CUs x 64 lanes x 2.4 GHz = 39.3 T of them per
+second.
 
-Other workloads (--workload): host34 (n=34 state as compressed chunks in
-pinned host memory), adjoint22 (adjoint gradient of a 6-layer ansatz at
-n=22), batch256 (256 circuits of 12..24 qubits, plus 64 batched adjoint
-parameter sets at n=18). Each prints its own JSON line.
+Other workloads (--workload): random20 (the small oracle-sized circuit),
+host34 (n=34 state as compressed chunks in pinned host memory), adjoint22
+(adjoint gradient of a 6-layer ansatz at n=22), batch256 (256 circuits of
+12..24 qubits, plus 64 batched adjoint parameter sets at n=18). Each prints
+its own JSON line.
 """
 
 from __future__ import annotations
@@ -44,9 +46,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0
+HBM_NOMINAL_GBS = 8000.0
 VALU_PEAK_GOPS = 256 * 64 * 2.4   # single-issue lane operations per ns = Gop/s
-MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "f64": 78.6}
+MFMA_NOMINAL_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "f64": 78.6}
 
 
 def parse():
@@ -61,6 +63,7 @@ def parse():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-probes", action="store_true", help="skip the measured roofline denominators")
     ap.add_argument("--no-extras", action="store_true", help="skip comparison runs outside the timed loop")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--workload", default="qft28",
@@ -100,10 +103,22 @@ def traffic_from_profiles(n_launch_bytes_key):
     return doc.get(n_launch_bytes_key)
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(n, x, gates, seconds):
-    """FP64 oracle on the same circuit: gates applied one by one from |x> until
-    about `seconds` of CPU time (a bounded sample of the workload)."""
-    import numpy as np
+    """FP64 oracle on the same circuit: gates applied in groups from |x> until
+    about `seconds` of wall time (a bounded sample of the workload), on every
+    host thread; then the same on one thread (a child process with
+    OMP_NUM_THREADS=1, a third of the time)."""
+    import subprocess
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
     psi = oracle.basis(n, x)
@@ -117,10 +132,55 @@ def cpu_baseline(n, x, gates, seconds):
             break
     dt = time.perf_counter() - t0
     del psi
-    return {"value": done * float(1 << n) / dt, "unit": "amplitude-gate updates/s",
-            "cores": threads, "kind": "oracle",
-            "sample": "FP64 uncompressed oracle simulator, first %d of %d gates of the same "
-                      "n=%d circuit from the same basis state (%.1f s wall)" % (done, len(gates), n, dt)}
+    out = {"value": done * float(1 << n) / dt, "unit": "amplitude-gate updates/s",
+           "cores": threads, "kind": "oracle", "cpu": cpu_model(),
+           "sample": "FP64 uncompressed oracle simulator, first %d of %d gates of the same "
+                     "n=%d circuit from the same basis state (%.1f s wall)" % (done, len(gates), n, dt)}
+    code = ("import sys,time; sys.path.insert(0, %r); import oracle; from workloads import qft_plus_random; "
+            "x, g = qft_plus_random(%d, 100, seed=%d); psi = oracle.basis(%d, x); t = time.perf_counter(); d = 0\n"
+            "while d < len(g) and time.perf_counter() - t < %f:\n"
+            "    psi = oracle.simulate(%d, g[d:d + 1], psi); d += 1\n"
+            "print(d, time.perf_counter() - t)" % (ROOT, n, 0, n, seconds / 3.0, n))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+        d1, t1 = r.stdout.split()[-2:]
+        out["one_thread"] = {"value": int(d1) * float(1 << n) / float(t1), "cores": 1,
+                             "sample": "first %s gates (%.1f s wall)" % (d1, float(t1))}
+    except Exception as e:   # reported, not fatal
+        out["one_thread"] = {"error": str(e)}
+    return out
+
+
+def codec_cpu_baseline(n, eb, log2c=20, seconds=4.0):
+    """The oracle's scalar codec (encode + decode of 2^log2c-amplitude complex64
+    chunks with Gaussian components of an n-qubit random state) on one host
+    thread and on every host thread (one chunk per call, calls on concurrent
+    threads: ctypes releases the interpreter lock). GB/s of uncompressed
+    amplitudes through encode and decode."""
+    import concurrent.futures as cf
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(5)
+    sig = 2.0 ** (-(n + 1) / 2.0)
+    chunk = (rng.standard_normal(1 << log2c) * sig + 1j * rng.standard_normal(1 << log2c) * sig).astype(np.complex64)
+
+    def one():
+        oracle.codec_decode(oracle.codec_encode(chunk, log2c, eb))
+
+    res = {}
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    for th in (1, threads):
+        done, t0 = 0, time.perf_counter()
+        with cf.ThreadPoolExecutor(th) as ex:
+            while time.perf_counter() - t0 < seconds / 2:
+                list(ex.map(lambda _: one(), range(th)))
+                done += th
+        dt = time.perf_counter() - t0
+        res["threads_%d" % th] = {"GBps": done * chunk.nbytes / dt / 1e9, "chunks": done, "s": dt}
+    res["note"] = ("oracle scalar codec, complex64 chunks of 2^%d amplitudes, sigma 2^-%g, eb %g, encode + decode"
+                   % (log2c, (n + 1) / 2.0, eb))
+    return res
 
 
 def main():
@@ -133,6 +193,7 @@ def main():
     import torch
 
     from paper_2309_16979_amd import Simulator, _lib
+    from paper_2309_16979_amd.msv import probe_denominators
     from workloads import qft_plus_random, zz_chain
 
     if not os.path.exists(_lib.LIB_PATH):
@@ -150,6 +211,8 @@ def main():
         {"random20": bench_random20, "host34": bench_host34, "adjoint22": bench_adjoint22,
          "batch256": bench_batch256}[a.workload](a)
         return
+    den = None if a.no_probes else probe_denominators()
+    hbm_peak = den["hbm_copy_GBps"] if den else HBM_NOMINAL_GBS
     n = a.n
     x, gates = qft_plus_random(n, 100, seed=a.seed)
     masks, coeffs = zz_chain(n)
@@ -160,56 +223,59 @@ def main():
         sim.apply(gates)
         return sim.expect_z(masks, coeffs)
 
-    opts = {"time_passes": 1}
+    def timed_loop(sim, steps):
+        acc = {"t_pass": 0.0, "passes": 0, "pass_bytes": 0, "pass_valu_ops": 0.0, "pass_issue_ops": 0.0,
+               "pass_mfma_flops": 0.0}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            zz = run(sim)
+            st = sim.stats()
+            for k in acc:
+                acc[k] += st[k]
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, zz, acc
+
+    opts = {"time_passes": 1, "plan_cache": 0}
     if a.tile:
         opts["tile_qubits"] = a.tile
     sim = Simulator(n, dtype="c64", eb=a.eb, chunk_qubits=min(20, n), k_max=a.k, mma=a.mma, options=opts)
     for _ in range(a.warmup):
         run(sim)
-    torch.cuda.synchronize()
-    t_pass = 0.0
-    n_pass = 0
-    pass_bytes = 0
-    valu_ops = 0.0
-    issue_ops = 0.0
-    mfma_flops = 0.0
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        zz = run(sim)
-        st = sim.stats()
-        t_pass += st["t_pass"]
-        n_pass += st["passes"]
-        pass_bytes += st["pass_bytes"]
-        valu_ops += st["pass_valu_ops"]
-        issue_ops += st["pass_issue_ops"]
-        mfma_flops += st["pass_mfma_flops"]
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    dt, zz, acc = timed_loop(sim, a.steps)
     value = a.steps * G * float(1 << n) / dt
     st = sim.stats()
+    # the same loop with the plan of identical calls reused (the offline stage once)
+    sim.set_option("plan_cache", 1)
+    run(sim)
+    dt_c, _, _ = timed_loop(sim, a.steps)
 
-    avg_pass = t_pass / max(1, n_pass)
-    bytes_per_pass = pass_bytes / max(1, n_pass)
-    valu_per_pass = valu_ops / max(1, n_pass)
-    issue_per_pass = issue_ops / max(1, n_pass)
+    n_pass = max(1, acc["passes"])
+    avg_pass = acc["t_pass"] / n_pass
+    bytes_per_pass = acc["pass_bytes"] / n_pass
+    valu_per_pass = acc["pass_valu_ops"] / n_pass
+    issue_per_pass = acc["pass_issue_ops"] / n_pass
     achieved_gbs = bytes_per_pass / avg_pass / 1e9 if avg_pass > 0 else 0.0
     achieved_gops = issue_per_pass / avg_pass / 1e9 if avg_pass > 0 else 0.0
     traffic = traffic_from_profiles("bytes_per_launch")
-    roof = {"bound": "alu", "achieved": round(achieved_gops, 1), "peak": round(VALU_PEAK_GOPS, 1),
-            "unit": "Gop/s (single-issue-equivalent vector lane operations)",
-            "frac": round(achieved_gops / VALU_PEAK_GOPS, 4),
-            "traffic": traffic,
+    roof = {"bound": "hbm", "achieved": round(achieved_gbs, 2), "peak": round(hbm_peak, 1), "unit": "GB/s",
+            "frac": round(achieved_gbs / hbm_peak, 4), "traffic": traffic,
+            "peak_source": "measured device copy kernel (msv_probe_hbm_copy)" if den else "nominal",
+            "nominal_peak": HBM_NOMINAL_GBS,
             "kernel": "pass_kernel<float,%d,true,true,*,%d>" % (a.tile or 12, 0 if a.k < 3 else 1),
-            "avg_launch_ms": round(avg_pass * 1e3, 4), "launches": n_pass,
-            "algorithmic_ops_per_launch": valu_per_pass,
-            "issue_equivalent_ops_per_launch": issue_per_pass,
-            "hbm": {"achieved": round(achieved_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-                    "algorithmic_bytes_per_launch": int(bytes_per_pass),
-                    "traffic_achieved": round(traffic / avg_pass / 1e9, 2) if traffic and avg_pass else None}}
-    if mfma_flops > 0 and avg_pass > 0:
-        roof["mfma"] = {"achieved": round(mfma_flops / max(1, n_pass) / avg_pass / 1e12, 3),
-                        "peak": MFMA_PEAK_TFLOPS[a.mma], "unit": "TFLOP/s"}
+            "avg_launch_ms": round(avg_pass * 1e3, 4), "launches": acc["passes"],
+            "algorithmic_bytes_per_launch": int(bytes_per_pass),
+            "traffic_over_algorithmic": round(traffic / bytes_per_pass, 3) if traffic else None,
+            "alu": {"achieved": round(achieved_gops, 1), "peak": round(VALU_PEAK_GOPS, 1),
+                    "unit": "Gop/s (single-issue-equivalent vector lane operations)",
+                    "frac": round(achieved_gops / VALU_PEAK_GOPS, 4),
+                    "algorithmic_ops_per_launch": valu_per_pass,
+                    "issue_equivalent_ops_per_launch": issue_per_pass}}
+    if acc["pass_mfma_flops"] > 0 and avg_pass > 0:
+        mk = {"f32": "mfma_f32_TFLOPs", "bf16": "mfma_bf16_TFLOPs", "f64": "mfma_f64_TFLOPs"}[a.mma]
+        roof["mfma"] = {"achieved": round(acc["pass_mfma_flops"] / n_pass / avg_pass / 1e12, 3),
+                        "peak": round(den[mk], 1) if den else MFMA_NOMINAL_TFLOPS[a.mma],
+                        "nominal_peak": MFMA_NOMINAL_TFLOPS[a.mma], "unit": "TFLOP/s"}
 
     out = {"metric": "amplitude-gate updates/sec incl. codec", "value": value,
            "unit": "amplitude-gate updates/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -218,10 +284,17 @@ def main():
            "data": "synthetic: seeded QFT|x> + 100 random gates",
            "config": {"workload": "qft+100 random, n=%d, complex64, chunk 2^20, eb=%g, device store" % (n, a.eb),
                       "n": n, "gates": G, "eb": a.eb, "k_max": a.k, "mma": a.mma,
-                      "passes": st["passes"], "fused_ops": st["fused_ops"]},
-           "roofline": roof}
+                      "passes": st["passes"], "fused_ops": st["fused_ops"], "planning": "every step"},
+           "roofline": roof,
+           "plan_reused": {"value": a.steps * G * float(1 << n) / dt_c, "ms_per_step": dt_c / a.steps * 1e3,
+                           "note": "same loop with option plan_cache=1 (passes and fusion planned once)"}}
+    if den:
+        out["denominators"] = den
     out["compression"] = {"ratio": st["ratio"], "qubits_gained": math.log2(st["ratio"]) if st["ratio"] > 0 else None,
-                          "compressed_bytes": st["compressed_bytes"], "max_err_all": st["max_err_all"],
+                          "compressed_bytes": st["compressed_bytes"], "reserved_bytes": st["reserved_bytes"],
+                          "uncompressed_bytes": st["uncompressed_bytes"],
+                          "reserved_over_uncompressed": st["reserved_bytes"] / st["uncompressed_bytes"],
+                          "max_err_all": st["max_err_all"],
                           "err_bound": st["err_bound"], "bound_violations": st["bound_violations"],
                           "zz_expectation": zz}
     sim.close()
@@ -264,13 +337,16 @@ def main():
                                           "mfma_ops": stk["mfma_ops"], "fused_ops": stk["fused_ops"]}
         out["mfma_sweep"] = sweep
         del amps_ref
+        plain_gbs = pst["pass_bytes"] / pst["t_pass"] / 1e9 if pst["t_pass"] else None
         out["comparators"] = {
             "c64_uncompressed_updates_per_s": G * float(1 << n) / t_plain,
-            "c64_uncompressed_pass_GBps": pst["pass_bytes"] / pst["t_pass"] / 1e9 if pst["t_pass"] else None,
+            "c64_uncompressed_pass_GBps": plain_gbs,
+            "c64_uncompressed_pass_hbm_frac": plain_gbs / hbm_peak if plain_gbs else None,
             "c128_uncompressed_updates_per_s": G * float(1 << n) / t_ref,
         }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, x, gates, a.cpu_seconds)
+        out["cpu_baseline"]["codec"] = codec_cpu_baseline(n, a.eb)
     print(json.dumps(out), flush=True)
 
 

@@ -108,11 +108,13 @@ typedef struct msv_stats {
     double pass_mfma_flops;      /* matrix-core flops of the same passes: 8*2^k
                                     per amplitude per fused op on MFMA            */
     double pass_issue_ops;       /* pass_valu_ops in single-issue equivalents: a
-                                    SIMD issues two FP32 add/mul/fma per four-cycle
-                                    slot but one FP64, conversion, compare or
-                                    cross-lane op, so gate ops of complex64 states
-                                    count 1/2 and the rest 1. The vector-ALU bound
-                                    of a pass is pass_issue_ops / (lanes x clock) */
+                                    SIMD issues two FP32 add/mul/fma or 32-bit
+                                    and/or/xor/add per four-cycle slot but one FP64,
+                                    conversion, compare or cross-lane op, so gate
+                                    ops of complex64 states and the W bit-plane ops
+                                    of each codec value count 1/2, the rest 1. The
+                                    vector-ALU bound of a pass is pass_issue_ops /
+                                    (lanes x clock)                               */
 } msv_stats;
 
 typedef struct msv_sim msv_sim;  /* opaque, library-owned */

@@ -60,6 +60,8 @@ EXPORTS = (
     "msv_expect_z", "msv_get_amplitudes", "msv_fidelity", "msv_get_stats", "msv_export_chunk",
     "msv_codec_encode", "msv_codec_decode", "msv_codec_bound", "msv_adjoint", "msv_batch_run",
     "msv_batch_adjoint", "msv_plan_export", "msv_get_pass_stats",
+    # include/msv_probe.h
+    "msv_probe_hbm_copy", "msv_probe_host_link", "msv_probe_mfma_peak",
 )
 
 _lib = None
@@ -109,6 +111,9 @@ def load():
         "msv_fidelity": ([P, P, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
         "msv_get_stats": ([P, C.POINTER(Stats)], C.c_int),
         "msv_get_pass_stats": ([P, P, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
+        "msv_probe_hbm_copy": ([C.c_size_t, C.c_int, C.POINTER(C.c_double)], C.c_int),
+        "msv_probe_host_link": ([C.c_size_t, C.c_int, C.c_int, C.POINTER(C.c_double)], C.c_int),
+        "msv_probe_mfma_peak": ([C.c_int, C.c_int, C.POINTER(C.c_double)], C.c_int),
         "msv_export_chunk": ([P, C.c_uint64, P, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
         "msv_codec_encode": ([C.c_int, C.c_int, C.c_double, P, P, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
         "msv_codec_decode": ([C.c_int, P, C.c_size_t, P], C.c_int),

@@ -274,7 +274,7 @@ int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOpt
         }
         s->stats.pass_bytes = bytes;
         // algorithmic work: gate arithmetic per amplitude and codec work per value
-        double gate = 0.0, codec = 0.0, mflops = 0.0;
+        double gate = 0.0, codec = 0.0, planes = 0.0, mflops = 0.0;
         const double amps = std::ldexp(1.0, s->n), vals = 2.0 * amps;
         words_in = (double)s->compressed_words;
         for (size_t p = 0; p < n_passes; ++p) {
@@ -286,12 +286,14 @@ int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOpt
                 else if (d.type == OP_MFMA) mflops += amps * 8.0 * (double)(1 << d.k);
             }
             if (s->compressed()) {
-                codec += 64.0 * (words_in + hout[3 * p + 2]) + 2.0 * 15.0 * vals;
+                planes += 64.0 * (words_in + hout[3 * p + 2]);
+                codec += 2.0 * 15.0 * vals;
                 words_in = hout[3 * p + 2];
             }
         }
-        s->stats.pass_valu_ops = gate + codec;
-        s->stats.pass_issue_ops = (s->is_double() ? 1.0 : 0.5) * gate + codec;
+        s->stats.pass_valu_ops = gate + planes + codec;
+        // bit-plane work is 32-bit AND / OR / shift, which dual-issue like FP32 arithmetic
+        s->stats.pass_issue_ops = (s->is_double() ? 1.0 : 0.5) * gate + 0.5 * planes + codec;
         s->stats.pass_mfma_flops = mflops;
     }
     if (n_passes) {

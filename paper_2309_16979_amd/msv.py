@@ -373,3 +373,22 @@ def _autograd():
 def adjoint_expectation(params, sim, gates, init_basis, masks, coeffs, checkpoints=()):
     """Differentiable expectation (torch): see AdjointExpectation."""
     return _autograd().apply(params, sim, gates, init_basis, masks, coeffs, tuple(checkpoints))
+
+
+def probe_denominators(hbm_bytes: int = 1 << 30, link_bytes: int = 256 << 20, mfma_iters: int = 4096) -> dict:
+    """Measured roofline denominators of the current device (include/msv_probe.h):
+    HBM copy GB/s (read + write), pinned host-link GB/s (H2D, D2H, both at
+    once) and dense matrix-core TFLOP/s (FP64, FP32, BF16)."""
+    Lb = load()
+    out = {}
+    v = C.c_double()
+    check(Lb.msv_probe_hbm_copy(hbm_bytes, 10, C.byref(v)))
+    out["hbm_copy_GBps"] = v.value
+    for name, d in (("h2d_GBps", 0), ("d2h_GBps", 1), ("bidir_GBps", 2)):
+        check(Lb.msv_probe_host_link(link_bytes, d, 5, C.byref(v)))
+        out[name] = v.value
+    for name, p in (("mfma_f64_TFLOPs", L.MMA_F64), ("mfma_f32_TFLOPs", L.MMA_F32), ("mfma_bf16_TFLOPs", L.MMA_BF16)):
+        check(Lb.msv_probe_mfma_peak(p, mfma_iters, C.byref(v)))
+        out[name] = v.value
+    out["sizes"] = {"hbm_copy_bytes": hbm_bytes, "link_bytes": link_bytes, "mfma_iters": mfma_iters}
+    return out

@@ -1,5 +1,6 @@
-"""The C-ABI library loads, exports every function include/msv.h declares, and
-rejects bad arguments before touching a device (CPU only: no compute calls)."""
+"""The C-ABI library loads, exports every function the headers in include/
+declare, and rejects bad arguments before touching a device (CPU only: no
+compute calls)."""
 
 import ctypes as C
 import os
@@ -8,7 +9,8 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "msv.h")
+HEADERS = sorted(os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+                 if f.endswith(".h"))
 
 
 @pytest.fixture(scope="module")
@@ -21,7 +23,7 @@ def L():
 
 
 def _declared():
-    txt = open(HEADER).read()
+    txt = "".join(open(h).read() for h in HEADERS)
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     return sorted(set(re.findall(r"\b(msv_[a-z0-9_]+)\s*\(", txt)))
 
