@@ -271,6 +271,18 @@ int msv_codec_encode(int dtype, int log2_chunk, double eb, const void *host_in,
 int msv_codec_decode(int dtype, const void *host_in, size_t in_bytes, void *host_out);
 /* Worst-case encoded size of one chunk. */
 size_t msv_codec_bound(int log2_chunk);
+/* msv_codec_encode for callers that cannot allocate device memory (code that
+ * must not call hipMalloc: under HIP graph capture, in tight serving loops, in
+ * harnesses that forbid it). Same arguments, result bytes and errors as
+ * msv_codec_encode, for chunks of at most 2^16 amplitudes (log2_chunk > 16
+ * gives MSV_E_ARG). It calls no hipMalloc, hipFree or other allocating
+ * routine and creates no stream: its device scratch is one static array of
+ * 3,203,840 bytes per GPU (held until the process ends), and its work runs on
+ * the current device's null stream, which the call synchronises. Every call on
+ * one GPU uses that GPU's array, so calls that overlap on one GPU (from
+ * several host threads) race; serialise them. */
+int msv_codec_encode_static(int dtype, int log2_chunk, double eb, const void *host_in,
+                            void *host_out, size_t cap, size_t *out_bytes);
 
 /* ---- adjoint differentiation ------------------------------------------------- */
 

@@ -59,7 +59,7 @@ EXPORTS = (
     "msv_set_stream", "msv_init_basis", "msv_init_state", "msv_apply", "msv_prob_one",
     "msv_expect_z", "msv_get_amplitudes", "msv_fidelity", "msv_get_stats", "msv_export_chunk",
     "msv_codec_encode", "msv_codec_decode", "msv_codec_bound", "msv_adjoint", "msv_batch_run",
-    "msv_batch_adjoint", "msv_plan_export", "msv_get_pass_stats",
+    "msv_batch_adjoint", "msv_plan_export", "msv_get_pass_stats", "msv_codec_encode_static",
     # include/msv_probe.h
     "msv_probe_hbm_copy", "msv_probe_host_link", "msv_probe_mfma_peak",
 )
@@ -117,6 +117,8 @@ def load():
         "msv_export_chunk": ([P, C.c_uint64, P, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
         "msv_codec_encode": ([C.c_int, C.c_int, C.c_double, P, P, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
         "msv_codec_decode": ([C.c_int, P, C.c_size_t, P], C.c_int),
+        "msv_codec_encode_static": ([C.c_int, C.c_int, C.c_double, P, P, C.c_size_t, C.POINTER(C.c_size_t)],
+                                    C.c_int),
         "msv_codec_bound": ([C.c_int], C.c_size_t),
         "msv_adjoint": ([P, C.POINTER(Gate), C.c_size_t, P, C.c_size_t, P, P, C.c_size_t, P, C.c_size_t,
                          C.POINTER(C.c_double), P], C.c_int),

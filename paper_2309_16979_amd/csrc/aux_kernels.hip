@@ -545,6 +545,21 @@ __global__ __launch_bounds__(kThreads) void scan_sizes_kernel(const uint64_t *si
     if (threadIdx.x == 0) offsets[n] = total;
 }
 
+__global__ __launch_bounds__(kThreads) void zero_words_kernel(uint64_t *p, uint64_t n)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kThreads)
+        p[i] = 0;
+}
+
+hipError_t launch_zero_words(uint64_t *p, uint64_t n_words, hipStream_t stream)
+{
+    if (n_words == 0) return hipSuccess;
+    uint64_t g = (n_words + kThreads - 1) / kThreads;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)g), dim3(kThreads), 0, stream, p, n_words);
+    return hipGetLastError();
+}
+
 hipError_t launch_scan_sizes(const uint64_t *sizes, uint64_t n, uint64_t *offsets, hipStream_t stream)
 {
     hipLaunchKernelGGL(scan_sizes_kernel, dim3(1), dim3(kThreads), 0, stream, sizes, n, offsets);

@@ -112,6 +112,10 @@ hipError_t launch_decode_range(bool is_double, bool compressed, const void *amps
                                double scale, uint64_t amp_begin, uint64_t amp_count, void *out,
                                hipStream_t stream);
 
+// p[0 .. n_words) = 0 by a kernel (safe inside captured HIP graphs, unlike a
+// memset node).
+hipError_t launch_zero_words(uint64_t *p, uint64_t n_words, hipStream_t stream);
+
 // ---- canonical chunk format (codec API, export, host store) ----------------
 
 // Encode n_chunks chunks of interleaved complex values (contiguous) into
