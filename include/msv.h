@@ -48,6 +48,8 @@ enum {
 };
 
 enum msv_dtype { MSV_C128 = 0, MSV_C64 = 1 };
+/* Meaning of the value given to msv_set_error_bound. */
+enum msv_eb_mode { MSV_EB_ABS = 0, MSV_EB_NORM_REL = 1 };
 enum msv_store { MSV_STORE_DEVICE = 0, MSV_STORE_HOST_PINNED = 1 };
 /* Arithmetic of fused dense gates: FP64 (complex128 states), FP32 or BF16
  * matrix-core inputs with FP32 accumulation (complex64 states). */
@@ -115,6 +117,10 @@ typedef struct msv_stats {
                                     of each codec value count 1/2, the rest 1. The
                                     vector-ALU bound of a pass is pass_issue_ops /
                                     (lanes x clock)                               */
+    uint64_t zero_groups_skipped;/* host store: chunk groups of the last apply whose
+                                    chunks were all ZERO; they stay ZERO under
+                                    unitary ops, so they were neither staged nor
+                                    run through the pass kernels                  */
 } msv_stats;
 
 typedef struct msv_sim msv_sim;  /* opaque, library-owned */
@@ -140,6 +146,19 @@ int msv_set_chunk_qubits(msv_sim *sim, int log2_chunk);
 /* Absolute error bound per real/imag component. 0 = uncompressed. eb > 0 turns
  * on the codec: codes q = rint(x / (2 eb)), |q| <= 2^30 - 1. */
 int msv_set_error_bound(msv_sim *sim, double eb);
+/* MSV_EB_ABS (default): the value of msv_set_error_bound is the absolute bound.
+ * MSV_EB_NORM_REL: it is relative to 2^(-n/2), the root-mean-square magnitude
+ * of the amplitudes of a unit-norm n-qubit state, so that the bound scales
+ * with the amplitudes instead of wiping them out as n grows (an absolute
+ * bound of 1e-4 is larger than every amplitude of a spread 28-qubit state).
+ * The absolute bound used is eb * 2^-(n/2) for even n and
+ * eb * 2^-((n-1)/2) * 0.7071067811865476 for odd n (both exact up to that
+ * one rounding); it is what msv_stats.err_bound and the chunk headers hold.
+ * Applies to later and earlier msv_set_error_bound calls alike; before
+ * msv_init_*. The codec is unchanged: this only chooses eb, as the paper
+ * leaves the compressor and its settings open (Sec. 2, end of the online
+ * stage). */
+int msv_set_error_bound_mode(msv_sim *sim, int mode);
 /* MSV_STORE_DEVICE (compressed chunks in HBM) or MSV_STORE_HOST_PINNED
  * (compressed chunks in pinned host memory, streamed per pass). */
 int msv_set_store(msv_sim *sim, int store);
@@ -254,6 +273,28 @@ int msv_export_chunk(msv_sim *sim, uint64_t chunk, void *host_out, size_t cap,
  * *used receives the doubles needed (call with cap 0 to size buf). */
 int msv_plan_export(int n_qubits, const msv_gate *gates, size_t n_gates, int log2_tile, int k_max,
                     int lookahead, int relabel, double *buf, size_t cap, size_t *used, uint64_t *n_passes);
+
+/* ---- circuit import -------------------------------------------------------------
+ * OpenQASM 2.0 text -> gate list, so that circuits exported by the frameworks
+ * the paper plugs the method into (Sec. 1 and 2: Qiskit, Cirq, UniQ) run
+ * here. Read: the header, include "qelib1.inc" (by name; no file is read),
+ * qreg / creg, user gate definitions (expanded inline), register
+ * broadcasting, parameter expressions (pi + - * / ^, unary minus, sin cos
+ * tan exp ln sqrt) and the standard gates by their OpenQASM 2.0 matrices:
+ * U/u3/u, u2, u1/p, rz (= u1: OpenQASM 2.0's rz differs from exp(-i t Z/2) by
+ * a global phase), rx, ry, x, y, z, h, s, sdg, t, tdg, sx, sxdg, id, CX/cx,
+ * cz, cy, ch, swap, cu1/cp, crz, crx, cry, cu3, rxx, rzz, and ccx / cswap as
+ * two-qubit gates (a Toffoli as CV CX CV^dagger CX CV with V = sqrt(X)).
+ * Gates without a native kind become MSV_U1 / MSV_U2 with matrices written
+ * to mats (gates[i].mat points into it). barrier and measure are skipped;
+ * reset, if and opaque give MSV_E_UNSUPPORTED; syntax errors, unknown gates
+ * and bad operands give MSV_E_ARG with the line in msv_last_error(NULL).
+ * Qubits of all quantum registers are numbered in declaration order.
+ * *n_qubits, *n_gates and *n_mat (doubles needed in mats) are always set;
+ * call with gates = mats = NULL to size the buffers (MSV_E_ARG when they are
+ * too small). Host only: no device work. */
+int msv_qasm_parse(const char *text, int *n_qubits, msv_gate *gates, size_t gate_cap, size_t *n_gates,
+                   double *mats, size_t mat_cap, size_t *n_mat);
 
 /* ---- codec on its own ---------------------------------------------------------
  * Format "MSVC" v1 for a chunk of C = 2^log2_chunk complex values:

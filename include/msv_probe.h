@@ -49,6 +49,33 @@ int msv_probe_host_link(size_t bytes, int direction, int reps, double *gbps);
  * *tflops = 2 M N K per op x ops / time / 1e12. */
 int msv_probe_mfma_peak(int precision, int iters, double *tflops);
 
+/* The paper's transfer experiment (Sec. 2, online stage step (2); Table 1):
+ * moving a 2^n-amplitude complex128 state between host and GPU memory by
+ *   MSV_XFER_SYNC           one synchronous hipMemcpy of the whole state;
+ *   MSV_XFER_PER_AMPLITUDE  one hipMemcpyAsync of 16 bytes per amplitude on a
+ *                           stream, as many calls as the state has amplitudes
+ *                           (the paper's "async copy");
+ *   MSV_XFER_STAGED_REMAP   one bulk copy into a device staging buffer, then a
+ *                           GPU kernel that places every amplitude (the paper's
+ *                           "buffer" strategy); device-to-host runs the kernel
+ *                           first and the bulk copy second.
+ * The remap places amplitude i of the host layout at device position
+ * p(i) = ((i mod 2^h) << (n - h)) | (i >> h), h = n / 2 (the two halves of the
+ * index bits exchanged: a chunked layout seen from the other side).
+ * to_device: 1 host-to-device, 0 device-to-host; pinned: 1 hipHostMalloc'd
+ * host buffer, 0 pageable (malloc'd). n_qubits in [6, 30]. The per-amplitude
+ * strategy issues at most max_calls (>= 1) copies, of amplitudes spread over
+ * the whole state, and extrapolates linearly; the others move everything.
+ * Each measurement follows one untimed copy of the same kind.
+ * *seconds = time of the whole-state transfer (extrapolated for the
+ * per-amplitude strategy), *per_call = seconds per copy call issued,
+ * *calls = copy calls issued. The data that arrives is checked against the
+ * source (every amplitude, or every sampled one): MSV_E_STATE if any differs.
+ * Allocates and frees its own buffers. */
+enum msv_xfer_strategy { MSV_XFER_SYNC = 0, MSV_XFER_PER_AMPLITUDE = 1, MSV_XFER_STAGED_REMAP = 2 };
+int msv_probe_transfer(int n_qubits, int strategy, int to_device, int pinned, size_t max_calls,
+                       double *seconds, double *per_call, size_t *calls);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,4 +8,4 @@ thin ctypes binding. Build with ``python -m paper_2309_16979_amd.build``.
 
 from ._lib import MsvError  # noqa: F401
 from .msv import (Simulator, codec_encode, codec_decode, codec_bound, gate_array,  # noqa: F401
-                  adjoint_expectation, batch_run, batch_adjoint, plan)
+                  adjoint_expectation, batch_run, batch_adjoint, plan, qasm_to_gates, probe_denominators)

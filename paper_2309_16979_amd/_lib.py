@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(HERE, "libmsv.so")
 
 OK, E_ARG, E_NOMEM, E_DEVICE, E_RANGE, E_STATE, E_CORRUPT, E_UNSUPPORTED, E_NORM = 0, -1, -2, -3, -4, -5, -6, -7, -8
 C128, C64 = 0, 1
+EB_ABS, EB_NORM_REL = 0, 1
 STORE_DEVICE, STORE_HOST_PINNED = 0, 1
 MMA_F64, MMA_F32, MMA_BF16 = 0, 1, 2
 KINDS = {name: i for i, name in enumerate(
@@ -34,7 +35,8 @@ class Stats(C.Structure):
             "t_h2d", "t_d2h", "t_kernel", "overlap")] + \
         [("bound_violations", C.c_uint64), ("kernel_launches", C.c_uint64),
          ("t_pass", C.c_double), ("pass_bytes", C.c_uint64), ("mfma_ops", C.c_uint64),
-         ("pass_valu_ops", C.c_double), ("pass_mfma_flops", C.c_double), ("pass_issue_ops", C.c_double)]
+         ("pass_valu_ops", C.c_double), ("pass_mfma_flops", C.c_double), ("pass_issue_ops", C.c_double),
+         ("zero_groups_skipped", C.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -60,8 +62,9 @@ EXPORTS = (
     "msv_expect_z", "msv_get_amplitudes", "msv_fidelity", "msv_get_stats", "msv_export_chunk",
     "msv_codec_encode", "msv_codec_decode", "msv_codec_bound", "msv_adjoint", "msv_batch_run",
     "msv_batch_adjoint", "msv_plan_export", "msv_get_pass_stats", "msv_codec_encode_static",
+    "msv_set_error_bound_mode", "msv_qasm_parse",
     # include/msv_probe.h
-    "msv_probe_hbm_copy", "msv_probe_host_link", "msv_probe_mfma_peak",
+    "msv_probe_hbm_copy", "msv_probe_host_link", "msv_probe_mfma_peak", "msv_probe_transfer",
 )
 
 _lib = None
@@ -97,6 +100,9 @@ def load():
         "msv_last_error": ([P], C.c_char_p),
         "msv_set_chunk_qubits": ([P, C.c_int], C.c_int),
         "msv_set_error_bound": ([P, C.c_double], C.c_int),
+        "msv_set_error_bound_mode": ([P, C.c_int], C.c_int),
+        "msv_qasm_parse": ([C.c_char_p, C.POINTER(C.c_int), P, C.c_size_t, C.POINTER(C.c_size_t), P, C.c_size_t,
+                            C.POINTER(C.c_size_t)], C.c_int),
         "msv_set_store": ([P, C.c_int], C.c_int),
         "msv_set_fusion": ([P, C.c_int, C.c_int], C.c_int),
         "msv_set_option": ([P, C.c_char_p, C.c_double], C.c_int),
@@ -114,6 +120,8 @@ def load():
         "msv_probe_hbm_copy": ([C.c_size_t, C.c_int, C.POINTER(C.c_double)], C.c_int),
         "msv_probe_host_link": ([C.c_size_t, C.c_int, C.c_int, C.POINTER(C.c_double)], C.c_int),
         "msv_probe_mfma_peak": ([C.c_int, C.c_int, C.POINTER(C.c_double)], C.c_int),
+        "msv_probe_transfer": ([C.c_int, C.c_int, C.c_int, C.c_int, C.c_size_t, C.POINTER(C.c_double),
+                                C.POINTER(C.c_double), C.POINTER(C.c_size_t)], C.c_int),
         "msv_export_chunk": ([P, C.c_uint64, P, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
         "msv_codec_encode": ([C.c_int, C.c_int, C.c_double, P, P, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
         "msv_codec_decode": ([C.c_int, P, C.c_size_t, P], C.c_int),

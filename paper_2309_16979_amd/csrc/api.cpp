@@ -394,14 +394,40 @@ int msv_set_chunk_qubits(msv_sim *s, int log2_chunk)
     return MSV_OK;
 }
 
+// Absolute bound for the handle's value and mode (see msv_set_error_bound_mode).
+static double absolute_eb(const msv_sim *s, double v)
+{
+    if (s->eb_mode != MSV_EB_NORM_REL || v == 0.0) return v;
+    const double r = std::ldexp(v, -(s->n / 2));
+    return (s->n & 1) ? r * 0.7071067811865476 : r;
+}
+
+static int apply_eb(msv_sim *s, double v)
+{
+    const double eb = absolute_eb(s, v);
+    if (eb > 0.0 && !(std::fabs(std::rint(1.0 / (2.0 * eb))) <= 1073741823.0))
+        return fail(s, MSV_E_RANGE, "eb too small: the code of 1.0 exceeds 2^30-1");
+    s->eb_value = v;
+    s->eb = eb;
+    return MSV_OK;
+}
+
 int msv_set_error_bound(msv_sim *s, double eb)
 {
     BEFORE_INIT(s);
     if (!(eb >= 0.0) || !std::isfinite(eb)) return fail(s, MSV_E_ARG, "eb must be finite and >= 0");
-    if (eb > 0.0 && !(std::fabs(std::rint(1.0 / (2.0 * eb))) <= 1073741823.0))
-        return fail(s, MSV_E_RANGE, "eb too small: the code of 1.0 exceeds 2^30-1");
-    s->eb = eb;
-    return MSV_OK;
+    return apply_eb(s, eb);
+}
+
+int msv_set_error_bound_mode(msv_sim *s, int mode)
+{
+    BEFORE_INIT(s);
+    if (mode != MSV_EB_ABS && mode != MSV_EB_NORM_REL) return fail(s, MSV_E_ARG, "unknown error-bound mode");
+    const int old = s->eb_mode;
+    s->eb_mode = mode;
+    const int st = apply_eb(s, s->eb_value);
+    if (st) s->eb_mode = old;
+    return st;
 }
 
 int msv_set_store(msv_sim *s, int store)

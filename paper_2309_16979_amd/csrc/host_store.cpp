@@ -197,6 +197,17 @@ PassPlan pass_plan(const msv_sim *s, const PassGeom &g)
     return p;
 }
 
+// Position of a ZERO chunk (the 32-byte header alone) in the arena of side
+// `side` for this pass, written once from the host copy kept at init.
+int zero_chunk_pos(msv_sim *s, int side, uint64_t *pos)
+{
+    HostStore &h = s->hs;
+    int st;
+    if ((st = arena_alloc(s, h.arena[side], 32, pos))) return st;
+    memcpy(h.arena[side].at(*pos), h.zero_hdr, 32);
+    return MSV_OK;
+}
+
 std::vector<uint64_t> group_chunks(const msv_sim *s, const PassPlan &p, uint64_t g0, uint64_t g1)
 {
     std::vector<uint64_t> out;
@@ -335,6 +346,7 @@ int init_host_store_basis(msv_sim *s, uint64_t index)
     if ((st = finish_batch(s, b, one, 0, &bytes))) return st;
     HIPCHK(s, hipStreamSynchronize(h.d2h));
     const uint64_t zpos = h.pos[0][0];
+    memcpy(h.zero_hdr, h.arena[0].at(zpos), 32);
     for (uint64_t c = 0; c < n_chunks; ++c) {
         h.pos[0][c] = zpos;
         h.bytes[0][c] = 32;
@@ -364,6 +376,18 @@ int init_host_store_state(msv_sim *s, const void *host)
     arena_reset(h.arena[0]);
     arena_reset(h.arena[1]);
     if ((st = clear_flags(s))) return st;
+    {
+        // the canonical ZERO chunk (its header), encoded on the GPU from
+        // all-zero widths and anchors; passes write it for all-zero groups
+        hipStream_t cs = s->stream();
+        BatchBufs &b = h.bb[0];
+        const uint64_t nb = (2ull << s->log2c) / 64;
+        HIPCHK(s, hipMemsetAsync(b.out_W.p, 0, nb, cs));
+        HIPCHK(s, hipMemsetAsync(b.out_A.p, 0, 4 * nb, cs));
+        if ((st = compact_batch(s, b, 1, nullptr, (const uint64_t *)b.out_heap.p))) return st;
+        HIPCHK(s, hipMemcpyAsync(h.zero_hdr, b.out_stage.p, 32, hipMemcpyDeviceToHost, cs));
+        HIPCHK(s, hipStreamSynchronize(cs));
+    }
     const uint64_t C = 1ull << s->log2c, n_chunks = 1ull << (s->n - s->log2c);
     const uint64_t m = h.cap_chunks;
     if ((st = dev_alloc(s, h.plain, s->elt() * C * m))) return st;
@@ -422,11 +446,42 @@ int apply_host_store(msv_sim *s, const std::vector<Prim> &prims, size_t n_gates)
     uint64_t h2d_bytes = 0, d2h_bytes = 0;
     double t_h2d = 0.0, t_d2h = 0.0, t_k = 0.0;
     const auto t0 = std::chrono::steady_clock::now();
+    uint64_t skipped = 0;
     for (size_t p = 0; p < geoms.size(); ++p) {
         const PassPlan pp = pass_plan(s, geoms[p]);
         const int in_side = h.cur, out_side = h.cur ^ 1;
         arena_reset(h.arena[out_side]);
-        const uint64_t n_batches = (pp.n_groups + pp.gpb - 1) / pp.gpb;
+        // A group whose chunks are all ZERO stays zero under the pass's
+        // (unitary) ops: its output chunks are ZERO headers and it is never
+        // staged. The other groups run as batches of at most gpb groups, each a
+        // contiguous run of groups (one tile range per launch).
+        std::vector<std::pair<uint64_t, uint64_t>> runs;   // [g0, g1)
+        uint64_t zpos_out = 0;
+        bool have_zero = false;
+        for (uint64_t g = 0; g < pp.n_groups; ++g) {
+            const std::vector<uint64_t> gc = group_chunks(s, pp, g, g + 1);
+            bool zero = true;
+            for (uint64_t c : gc) zero = zero && h.bytes[in_side][c] <= 32;
+            if (zero) {
+                if (!have_zero) {
+                    if ((st = zero_chunk_pos(s, out_side, &zpos_out))) return st;
+                    have_zero = true;
+                }
+                for (uint64_t c : gc) {
+                    h.pos[out_side][c] = zpos_out;
+                    h.bytes[out_side][c] = 32;
+                }
+                ++skipped;
+                continue;
+            }
+            if (!runs.empty() && runs.back().second == g && runs.back().second - runs.back().first < pp.gpb)
+                ++runs.back().second;
+            else
+                runs.push_back({g, g + 1});
+        }
+        // the statistics sum every tile's partials: skipped tiles contribute zeros
+        HIPCHK(s, hipMemsetAsync(h.part.p, 0, 3 * 8 * tiles_per_pass, cs));
+        const uint64_t n_batches = runs.size();
         // timing events of every batch: H2D, kernels, D2H (begin, end each)
         while (h.tev.size() < 6 * n_batches) {
             hipEvent_t e;
@@ -439,7 +494,7 @@ int apply_host_store(msv_sim *s, const std::vector<Prim> &prims, size_t n_gates)
         for (uint64_t bi = 0; bi < n_batches; ++bi) {
             const int si = (int)(bi & 1);
             BatchBufs &b = h.bb[si];
-            const uint64_t g0 = bi * pp.gpb, g1 = std::min(pp.n_groups, g0 + pp.gpb);
+            const uint64_t g0 = runs[bi].first, g1 = runs[bi].second;
             std::vector<uint64_t> chunks = group_chunks(s, pp, g0, g1);
             // inputs of this buffer set were last read by the kernels of batch bi-2
             HIPCHK(s, hipStreamWaitEvent(h.h2d, b.k_done, 0));
@@ -518,6 +573,7 @@ int apply_host_store(msv_sim *s, const std::vector<Prim> &prims, size_t n_gates)
     if ((st = read_flags(s, &f))) return st;
     s->stats.passes = geoms.size();
     s->stats.fused_ops = ops.size();
+    s->stats.zero_groups_skipped = skipped;
     s->pass_log.assign(hs.begin(), hs.begin() + 3 * geoms.size());
     s->stats.h2d_bytes = h2d_bytes;
     s->stats.d2h_bytes = d2h_bytes;

@@ -7,7 +7,9 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
+#include <vector>
 
 #include "../../include/msv_probe.h"
 
@@ -318,3 +320,147 @@ int msv_probe_mfma_peak(int precision, int iters, double *tflops)
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------- transfers
+
+namespace {
+
+// dst[p(i)] = src[i] (to_device) or dst[i] = src[p(i)], for complex128
+// amplitudes moved as 16-byte words; p exchanges the low h and high n - h
+// index bits.
+__global__ __launch_bounds__(256) void remap_kernel(const u4v *__restrict__ src, u4v *__restrict__ dst, int n, int h,
+                                                    int scatter)
+{
+    const uint64_t N = 1ull << n, lo = (1ull << h) - 1;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (uint64_t)gridDim.x * 256) {
+        const uint64_t p = ((i & lo) << (n - h)) | (i >> h);
+        if (scatter) dst[p] = src[i];
+        else dst[i] = src[p];
+    }
+}
+
+uint64_t remap_index(uint64_t i, int n, int h) { return ((i & ((1ull << h) - 1)) << (n - h)) | (i >> h); }
+
+struct HostBuf {
+    void *p = nullptr;
+    bool pinned = false;
+    ~HostBuf()
+    {
+        if (!p) return;
+        if (pinned) (void)hipHostFree(p);
+        else free(p);
+    }
+};
+
+}  // namespace
+
+extern "C" int msv_probe_transfer(int n, int strategy, int to_device, int pinned, size_t max_calls, double *seconds,
+                                  double *per_call, size_t *calls)
+{
+    if (n < 6 || n > 30 || strategy < MSV_XFER_SYNC || strategy > MSV_XFER_STAGED_REMAP || !seconds || !per_call ||
+        !calls || max_calls < 1)
+        return MSV_E_ARG;
+    const uint64_t N = 1ull << n, bytes = 16 * N;
+    const int h = n / 2;
+    HostBuf hb;
+    hb.pinned = pinned != 0;
+    if (hb.pinned) PCHK(hipHostMalloc(&hb.p, bytes, hipHostMallocDefault));
+    else if (!(hb.p = aligned_alloc(4096, bytes))) return MSV_E_NOMEM;
+    HipBuf dev, stage;
+    PCHK(hipMalloc(&dev.p, bytes));
+    if (strategy == MSV_XFER_STAGED_REMAP) PCHK(hipMalloc(&stage.p, bytes));
+    Stream st;
+    PCHK(hipStreamCreateWithFlags(&st.s, hipStreamNonBlocking));
+    double *hv = (double *)hb.p;
+    // source data: amplitude i = (i, -i) in the host layout
+    std::vector<double> check;
+    if (to_device) {
+        for (uint64_t i = 0; i < N; ++i) { hv[2 * i] = (double)i; hv[2 * i + 1] = -(double)i; }
+        PCHK(hipMemset(dev.p, 0xff, bytes));
+    } else {
+        // device state in the device layout, filled by a sync copy and (for
+        // the staged strategy) the inverse placement, from a temporary buffer
+        std::vector<double> tmp(2 * N);
+        for (uint64_t i = 0; i < N; ++i) {
+            const uint64_t q = strategy == MSV_XFER_STAGED_REMAP ? remap_index(i, n, h) : i;
+            tmp[2 * q] = (double)i;
+            tmp[2 * q + 1] = -(double)i;
+        }
+        PCHK(hipMemcpy(dev.p, tmp.data(), bytes, hipMemcpyHostToDevice));
+        memset(hb.p, 0xff, bytes);
+    }
+    // warm-up: the same kind of copy once, untimed (first-touch costs of the
+    // buffers and the copy path stay out of the measurement)
+    if (strategy == MSV_XFER_PER_AMPLITUDE) {
+        for (int k = 0; k < 64; ++k) {
+            const uint64_t i = (uint64_t)k * (N / 64);
+            if (to_device)
+                PCHK(hipMemcpyAsync((uint8_t *)dev.p + 16 * i, (uint8_t *)hb.p + 16 * i, 16, hipMemcpyHostToDevice, st.s));
+            else
+                PCHK(hipMemcpyAsync((uint8_t *)hb.p + 16 * i, (uint8_t *)dev.p + 16 * i, 16, hipMemcpyDeviceToHost, st.s));
+        }
+        PCHK(hipStreamSynchronize(st.s));
+    } else {
+        void *scratch_dev = strategy == MSV_XFER_STAGED_REMAP ? stage.p : dev.p;
+        if (to_device) PCHK(hipMemcpy(scratch_dev, hb.p, bytes, hipMemcpyHostToDevice));
+        else if (strategy == MSV_XFER_STAGED_REMAP) PCHK(hipMemcpy(hb.p, stage.p, bytes, hipMemcpyDeviceToHost));
+        else PCHK(hipMemcpy(hb.p, dev.p, bytes, hipMemcpyDeviceToHost));
+    }
+    PCHK(hipDeviceSynchronize());
+    // the destination is overwritten again, so the check below sees only the timed copies
+    if (to_device) PCHK(hipMemset(dev.p, 0xff, bytes));
+    else memset(hb.p, 0xff, bytes);
+    PCHK(hipDeviceSynchronize());
+    uint64_t n_calls = 1;
+    const auto t0 = std::chrono::steady_clock::now();
+    if (strategy == MSV_XFER_SYNC) {
+        if (to_device) PCHK(hipMemcpy(dev.p, hb.p, bytes, hipMemcpyHostToDevice));
+        else PCHK(hipMemcpy(hb.p, dev.p, bytes, hipMemcpyDeviceToHost));
+    } else if (strategy == MSV_XFER_PER_AMPLITUDE) {
+        n_calls = std::min<uint64_t>(N, max_calls);
+        const uint64_t stride = N / n_calls;
+        for (uint64_t k = 0; k < n_calls; ++k) {
+            const uint64_t i = k * stride;
+            if (to_device)
+                PCHK(hipMemcpyAsync((uint8_t *)dev.p + 16 * i, (uint8_t *)hb.p + 16 * i, 16, hipMemcpyHostToDevice, st.s));
+            else
+                PCHK(hipMemcpyAsync((uint8_t *)hb.p + 16 * i, (uint8_t *)dev.p + 16 * i, 16, hipMemcpyDeviceToHost, st.s));
+        }
+        PCHK(hipStreamSynchronize(st.s));
+    } else {
+        int cus = 0;
+        if (int e = device_cus(&cus)) return e;
+        const dim3 grid((unsigned)std::min<uint64_t>((N + 255) / 256, (uint64_t)cus * 16)), block(256);
+        n_calls = 2;
+        if (to_device) {
+            PCHK(hipMemcpyAsync(stage.p, hb.p, bytes, hipMemcpyHostToDevice, st.s));
+            hipLaunchKernelGGL(remap_kernel, grid, block, 0, st.s, (const u4v *)stage.p, (u4v *)dev.p, n, h, 1);
+            PCHK(hipGetLastError());
+        } else {
+            hipLaunchKernelGGL(remap_kernel, grid, block, 0, st.s, (const u4v *)dev.p, (u4v *)stage.p, n, h, 0);
+            PCHK(hipGetLastError());
+            PCHK(hipMemcpyAsync(hb.p, stage.p, bytes, hipMemcpyDeviceToHost, st.s));
+        }
+        PCHK(hipStreamSynchronize(st.s));
+    }
+    const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *calls = n_calls;
+    *per_call = dt / (double)n_calls;
+    *seconds = strategy == MSV_XFER_PER_AMPLITUDE ? dt * (double)N / (double)n_calls : dt;
+    // check what arrived
+    const uint64_t step = strategy == MSV_XFER_PER_AMPLITUDE ? N / n_calls : 1;
+    std::vector<double> got;
+    const double *g = hv;
+    if (to_device) {
+        got.resize(2 * N);
+        PCHK(hipMemcpy(got.data(), dev.p, bytes, hipMemcpyDeviceToHost));
+        g = got.data();
+    }
+    for (uint64_t i = 0; i < N; i += step) {
+        // to_device: device position of host amplitude i; from the device:
+        // host position i holds amplitude i
+        const uint64_t at = (to_device && strategy == MSV_XFER_STAGED_REMAP) ? remap_index(i, n, h) : i;
+        if (g[2 * at] != (double)i || g[2 * at + 1] != -(double)i) return MSV_E_STATE;
+    }
+    return MSV_OK;
+}

@@ -62,6 +62,7 @@ struct HostStore {
     DevMem zero_blob, part, plain;
     hipStream_t h2d = nullptr, d2h = nullptr;
     uint64_t cap_chunks = 0;   // chunks per batch buffer
+    uint8_t zero_hdr[32] = {}; // canonical header of a ZERO chunk (set at init)
     std::vector<hipEvent_t> tev;   // timing events, 6 per batch of a pass
     bool ready = false;
 };
@@ -75,7 +76,9 @@ struct Workspace {
 
 struct msv_sim {
     int n = 0, dtype = MSV_C64, log2c = 20, store = MSV_STORE_DEVICE;
-    double eb = 0.0;
+    double eb = 0.0;                 // absolute bound used by the codec
+    double eb_value = 0.0;           // value given to msv_set_error_bound
+    int eb_mode = MSV_EB_ABS;
     int k_max = 2, mma = MSV_MMA_F32, tile_bits = 0, renorm = 0, check_bound = 1, mfma_min_k = 3;
     int batch_chunks = 0;
     int time_passes = 0;

@@ -82,13 +82,14 @@ class Simulator:
     """An n-qubit state held as compressed chunks (eb > 0) or plain amplitudes.
 
     Parameters mirror the setters of the C ABI: dtype "c128"/"c64", eb the
-    absolute error bound per component (0 = uncompressed), chunk_qubits,
+    error bound per component (0 = uncompressed), eb_mode "abs" (eb is
+    absolute) or "rel" (eb is relative to 2^(-n/2)), chunk_qubits,
     store "device"/"host", k_max fusion width, mma "f64"/"f32"/"bf16",
     options a dict for msv_set_option. use_torch routes device memory and the
     stream through PyTorch (default when a GPU is visible to torch).
     """
 
-    def __init__(self, n: int, dtype: str = "c64", eb: float = 0.0,
+    def __init__(self, n: int, dtype: str = "c64", eb: float = 0.0, eb_mode: str = "abs",
                  chunk_qubits: Optional[int] = None, store: str = "device", k_max: int = 2,
                  mma: Optional[str] = None, options: Optional[dict] = None,
                  use_torch: Optional[bool] = None):
@@ -103,6 +104,7 @@ class Simulator:
         try:
             if chunk_qubits is not None:
                 check(self._L.msv_set_chunk_qubits(h, chunk_qubits), h)
+            check(self._L.msv_set_error_bound_mode(h, {"abs": L.EB_ABS, "rel": L.EB_NORM_REL}[eb_mode]), h)
             check(self._L.msv_set_error_bound(h, float(eb)), h)
             check(self._L.msv_set_store(h, _STORE[store]), h)
             if mma is None:
@@ -392,3 +394,52 @@ def probe_denominators(hbm_bytes: int = 1 << 30, link_bytes: int = 256 << 20, mf
         out[name] = v.value
     out["sizes"] = {"hbm_copy_bytes": hbm_bytes, "link_bytes": link_bytes, "mfma_iters": mfma_iters}
     return out
+
+
+class QasmGate:
+    """One gate read from OpenQASM (the fields gate_array marshals)."""
+
+    __slots__ = ("name", "q0", "q1", "theta", "param", "mat")
+
+    def __init__(self, name, q0, q1=-1, theta=0.0, param=-1, mat=None):
+        self.name, self.q0, self.q1, self.theta, self.param, self.mat = name, q0, q1, theta, param, mat
+
+    def __repr__(self):
+        return "QasmGate(%s, %d, %d, %g)" % (self.name, self.q0, self.q1, self.theta)
+
+
+def qasm_to_gates(text: str):
+    """Parse OpenQASM 2.0 text (msv_qasm_parse). Returns (n_qubits, gates)."""
+    Lb = load()
+    b = text.encode()
+    nq, ng, nm = C.c_int(0), C.c_size_t(0), C.c_size_t(0)
+    check(Lb.msv_qasm_parse(b, C.byref(nq), None, 0, C.byref(ng), None, 0, C.byref(nm)))
+    arr = (L.Gate * max(1, ng.value))()
+    mats = np.zeros(max(1, nm.value), dtype=np.float64)
+    check(Lb.msv_qasm_parse(b, C.byref(nq), arr, ng.value, C.byref(ng), mats.ctypes.data, mats.size, C.byref(nm)))
+    names = {v: k for k, v in L.KINDS.items()}
+    base = mats.ctypes.data
+    out = []
+    for i in range(ng.value):
+        g = arr[i]
+        m = None
+        if g.kind in (L.KINDS["U1"], L.KINDS["U2"]):
+            d = 2 if g.kind == L.KINDS["U1"] else 4
+            off = (C.cast(g.mat, C.c_void_p).value - base) // 8
+            v = mats[off:off + 2 * d * d]
+            m = (v[0::2] + 1j * v[1::2]).reshape(d, d)
+        out.append(QasmGate(names[g.kind], g.q0, g.q1, g.theta, -1, m))
+    return nq.value, out
+
+
+XFER_STRATEGIES = {"sync": 0, "per_amplitude": 1, "staged_remap": 2}
+
+
+def probe_transfer(n: int, strategy: str, to_device: bool, pinned: bool, max_calls: int = 1 << 15) -> dict:
+    """Whole-state host<->GPU transfer of a 2^n complex128 state by one of the
+    paper's three strategies (msv_probe_transfer); the arrived data is checked."""
+    Lb = load()
+    sec, per, calls = C.c_double(), C.c_double(), C.c_size_t()
+    check(Lb.msv_probe_transfer(n, XFER_STRATEGIES[strategy], int(bool(to_device)), int(bool(pinned)), max_calls,
+                                C.byref(sec), C.byref(per), C.byref(calls)))
+    return {"seconds": sec.value, "per_call_s": per.value, "calls": calls.value}

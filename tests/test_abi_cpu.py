@@ -57,6 +57,12 @@ def test_create_validation(L):
         assert L.msv_set_error_bound(h, float("nan")) == _lib.E_ARG
         assert L.msv_set_error_bound(h, 1e-12) == _lib.E_RANGE   # code of 1.0 > 2^30-1
         assert L.msv_set_error_bound(h, 1e-4) == _lib.OK
+        assert L.msv_set_error_bound_mode(h, 7) == _lib.E_ARG
+        assert L.msv_set_error_bound_mode(h, _lib.EB_NORM_REL) == _lib.OK
+        assert L.msv_set_error_bound(h, 1e-9) == _lib.E_RANGE     # 1e-9 * 2^-5: code of 1.0 too large
+        assert L.msv_set_error_bound(h, 0.1) == _lib.OK
+        assert L.msv_set_error_bound_mode(h, _lib.EB_ABS) == _lib.OK
+        assert L.msv_set_error_bound(h, 1e-4) == _lib.OK
         assert L.msv_set_fusion(h, 0, _lib.MMA_F32) == _lib.E_ARG
         assert L.msv_set_fusion(h, 6, _lib.MMA_F32) == _lib.E_ARG
         assert L.msv_set_fusion(h, 3, _lib.MMA_F64) == _lib.E_ARG  # c64 state

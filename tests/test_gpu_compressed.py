@@ -200,3 +200,48 @@ def test_host_store_crossing_circuit_against_oracle():
     # |p1 - p1_ref| <= 2 ||e|| + ||e||^2 with ||e|| <= P eb' sqrt(2^(n+1))
     e = P * st["err_bound"] * math.sqrt(2.0 * (1 << n))
     assert abs(p1 - oracle.prob_one(ref, n - 1)) <= 2 * e + e * e
+
+
+def test_norm_relative_eb_is_the_scaled_absolute_bound():
+    """MSV_EB_NORM_REL with value v runs exactly the absolute bound
+    v 2^-(n/2) (odd n: v 2^-((n-1)/2) / sqrt(2), rounded once): identical
+    chunk bytes and amplitudes."""
+    for n in (15, 16):
+        gates = random_circuit(n, 8, seed=n)
+        v = 0.05
+        eb = math.ldexp(v, -(n // 2)) * (0.7071067811865476 if n % 2 else 1.0)
+        out = []
+        for mode, val in (("rel", v), ("abs", eb)):
+            log("eb mode", mode, n)
+            with _sim(n, "c64", val, eb_mode=mode, chunk_qubits=10) as s:
+                s.init_basis(3)
+                s.apply(gates)
+                out.append((s.amplitudes(), s.export_chunk(1), s.stats()["err_bound"]))
+        assert np.array_equal(out[0][0].view(np.uint8), out[1][0].view(np.uint8))
+        assert out[0][1] == out[1][1] and out[0][2] == out[1][2]
+        assert oracle.codec_header(out[0][1])["eb"] == eb
+
+
+def test_host_store_skips_zero_groups_bitwise():
+    """A state that lives in a few chunks (gates on qubits 0..15 only, chunks
+    of 2^14 amplitudes, n = 24): chunk groups that are all ZERO stay ZERO under
+    the pass's unitary ops, so the host store skips them (no staging, no
+    kernels) and still writes exactly the device store's chunks."""
+    from workloads import random_circuit as rc
+    n, lc, eb = 24, 14, 1e-5
+    gates = rc(16, 10, seed=8)
+    out = {}
+    for store in ("device", "host"):
+        log("zero groups", store)
+        with _sim(n, "c64", eb, chunk_qubits=lc, store=store) as s:
+            s.init_basis(0)
+            s.apply(gates)
+            st = s.stats()
+            out[store] = (s.amplitudes(0, 1 << 16), [s.export_chunk(c) for c in (0, 3, 4, 77, 1023)], st)
+    a_d, ch_d, st_d = out["device"]
+    a_h, ch_h, st_h = out["host"]
+    assert np.array_equal(a_d.view(np.uint8), a_h.view(np.uint8))
+    assert ch_d == ch_h
+    assert all(len(c) == 32 for c in ch_h[2:])
+    assert st_h["zero_groups_skipped"] > 0 and st_h["passes"] == st_d["passes"]
+    print("zero groups skipped:", st_h["zero_groups_skipped"], "passes", st_h["passes"])

@@ -81,3 +81,24 @@ def test_headline_compressed_fidelity(case):
     print("headline c64 eb=1e-5: passes %d, F_raw %.6f, F_norm %.6f (budget %.4f), ratio %.2f"
           % (P, fr, fn, budget, st["ratio"]))
     assert fn >= budget
+
+
+@pytest.mark.parametrize("eb_rel", [1e-1, 1e-2])
+def test_headline_norm_relative_eb(case, eb_rel):
+    """Norm-relative error bound (eb = eb_rel 2^-(n/2)): the absolute bounds
+    1e-4 and 1e-3 are larger than every amplitude of this state (|psi_i| =
+    2^-14 after the QFT) and quantise it to zero; a bound relative to the
+    amplitude scale keeps F_norm >= 0.9 while still compressing."""
+    x, gates, ref = case
+    log("headline c64 eb_rel", eb_rel)
+    with _sim(eb=eb_rel, eb_mode="rel") as s:
+        s.init_basis(x)
+        s.apply(gates)
+        st = s.stats()
+        fr, fn = s.fidelity(ref)
+    eb = math.ldexp(eb_rel, -(N // 2))
+    assert eb * (1 + 2.0 ** -20) < st["err_bound"] <= eb * (1 + 2.0 ** -20) + 2.0 ** -22
+    assert st["bound_violations"] == 0
+    print("headline c64 eb_rel=%g (eb=%.3g): passes %d, F_norm %.6f, ratio %.2f"
+          % (eb_rel, eb, st["passes"], fn, st["ratio"]))
+    assert fn >= 0.9 and st["ratio"] > 1.0
