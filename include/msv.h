@@ -198,8 +198,9 @@ int msv_set_fusion(msv_sim *sim, int k_max, int mma_precision);
  *                  gates (compared exactly, matrices included) under the same
  *                  options; the plan is the offline stage of the method.
  *                  0 = plan every call
- *   "autotune"     1 = choose fusion width and tile size per msv_apply from a
- *                  cost model calibrated once per process on the GPU */
+ *   "autotune"     1 = choose fusion width and tile size per msv_apply from
+ *                  the fixed cost model (the same plan in every process);
+ *                  2 = from the model measured once in this process; 0 = off */
 int msv_set_option(msv_sim *sim, const char *key, double value);
 /* Device memory provider (e.g. a framework's caching allocator). alloc returns
  * NULL on failure; both are called on the calling thread. Without it the
@@ -349,22 +350,37 @@ typedef struct msv_circuit {
 } msv_circuit;
 
 typedef struct msv_batch_opts {
-    int32_t autotune;        /* 1 = choose fusion width and tile per circuit   */
+    int32_t autotune;        /* 0 = the k_max and log2_tile below; 1 = choose
+                                the fusion width per circuit and the tile size
+                                of the batch by the fixed cost model (the same
+                                plans, hence results, in every process);
+                                2 = the same with the model measured in this
+                                process                                        */
     int32_t k_max;           /* used when autotune = 0                          */
     int32_t log2_tile;       /* used when autotune = 0 (0 = automatic)          */
     int32_t mma_precision;   /* enum msv_mma                                    */
 } msv_batch_opts;
 
-/* Run count circuits (8..30 qubits each, compressed with eb > 0): pass level l
- * of every circuit runs in one launch per tile size (a workgroup finds its
- * circuit by binary search over the launch's tile counts), so small circuits
- * together fill the GPU. With opts->autotune the fusion width and tile size
- * of each circuit minimise a cost model calibrated once per process on the
- * GPU. amps_out[i] (host, 2^n_i complex of dtype) may be NULL to skip the
- * copy; stats_out aggregates. MSV_E_NOMEM when the stores do not fit. */
+/* Run count circuits (8..30 qubits each, compressed with eb > 0) in ONE
+ * launch of persistent workgroups (the batching form of the hot path: many
+ * circuits in one persistent launch). Work items are (circuit, pass level,
+ * tile) in level-major order on a device queue; a workgroup takes the next
+ * item with an atomic add and runs it once its circuit's previous level is
+ * complete (per-circuit completion counters, device-scope fences), so small
+ * circuits fill the GPU together and nothing returns to the host between
+ * levels. All circuits share the tile size (at most 2^min(12, smallest n)).
+ * amps_out[i] (host, 2^n_i complex of dtype) may be NULL to skip the copy;
+ * stats_out aggregates (kernel_launches = 1). MSV_E_NOMEM when the stores do
+ * not fit; MSV_E_DEVICE if a dependency wait ran past its limit. */
 int msv_batch_run(const msv_circuit *circuits, size_t count, int dtype, double eb,
                   const msv_batch_opts *opts, void *const *amps_out,
                   msv_stats *stats_out);
+/* Measure the autotuner's cost model on the current device (complex64 or
+ * complex128 states, n = 20, eb = 1e-5): model[0..2] ns per amplitude of a
+ * pass with tile sizes 2^10..2^12, model[3..7] of a dense op of width 1..5,
+ * model[8] of a diagonal op, model[9] of a controlled phase; cap >= 10. The
+ * fixed table of autotune mode 1 came from this call on an MI355X. */
+int msv_autotune_calibrate(int dtype, double *model, size_t cap);
 /* Adjoint gradients of one ansatz for n_sets parameter sets (params is
  * n_sets x n_params, row-major); expvals[n_sets], grads[n_sets x n_params].
  * Sets run on up to 8 concurrent workers, each with its own simulator and

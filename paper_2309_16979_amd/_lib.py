@@ -62,7 +62,7 @@ EXPORTS = (
     "msv_expect_z", "msv_get_amplitudes", "msv_fidelity", "msv_get_stats", "msv_export_chunk",
     "msv_codec_encode", "msv_codec_decode", "msv_codec_bound", "msv_adjoint", "msv_batch_run",
     "msv_batch_adjoint", "msv_plan_export", "msv_get_pass_stats", "msv_codec_encode_static",
-    "msv_set_error_bound_mode", "msv_qasm_parse",
+    "msv_set_error_bound_mode", "msv_qasm_parse", "msv_autotune_calibrate",
     # include/msv_probe.h
     "msv_probe_hbm_copy", "msv_probe_host_link", "msv_probe_mfma_peak", "msv_probe_transfer",
 )
@@ -101,6 +101,7 @@ def load():
         "msv_set_chunk_qubits": ([P, C.c_int], C.c_int),
         "msv_set_error_bound": ([P, C.c_double], C.c_int),
         "msv_set_error_bound_mode": ([P, C.c_int], C.c_int),
+        "msv_autotune_calibrate": ([C.c_int, P, C.c_size_t], C.c_int),
         "msv_qasm_parse": ([C.c_char_p, C.POINTER(C.c_int), P, C.c_size_t, C.POINTER(C.c_size_t), P, C.c_size_t,
                             C.POINTER(C.c_size_t)], C.c_int),
         "msv_set_store": ([P, C.c_int], C.c_int),

@@ -478,7 +478,8 @@ int msv_set_option(msv_sim *s, const char *key, double v)
         s->plan_cache = v != 0.0;
         s->plan_key.clear();
     } else if (!strcmp(key, "autotune")) {
-        s->autotune = v != 0.0;
+        if (v != iv || iv < 0 || iv > 2) return fail(s, MSV_E_ARG, "autotune in 0..2");
+        s->autotune = iv;
     } else if (!strcmp(key, "time_passes")) {
         s->time_passes = v != 0.0;
     } else if (!strcmp(key, "batch_chunks")) {
@@ -658,7 +659,8 @@ int msv_apply(msv_sim *s, const msv_gate *gates, size_t n_gates)
         // the offline stage depends only on the gates and these options
         std::vector<uint64_t> key = {(uint64_t)s->n, (uint64_t)s->dtype, (uint64_t)o.tb, (uint64_t)o.k_max,
                                      (uint64_t)o.mfma_min_k, (uint64_t)o.mma, (uint64_t)o.segments,
-                                     (uint64_t)o.lookahead, (uint64_t)relabel, (uint64_t)tune, n_gates};
+                                     (uint64_t)o.lookahead, (uint64_t)relabel,
+                                     (uint64_t)(tune ? s->autotune : 0), n_gates};
         for (size_t i = 0; i < n_gates; ++i) {
             const msv_gate &g = gates[i];
             uint64_t th;
@@ -682,7 +684,7 @@ int msv_apply(msv_sim *s, const msv_gate *gates, size_t n_gates)
             const std::vector<Prim> &pl = relabel ? renamed : prims;
             if (tune) {
                 int k = o.k_max, tb = o.tb;
-                if ((st = autotune(s->is_double(), s->stream(), pl, s->n, &k, &tb, &passes))) return st;
+                if ((st = autotune(s->is_double(), s->autotune, s->stream(), pl, s->n, &k, &tb, &passes))) return st;
                 o.k_max = s->tuned_k = k;
                 o.tb = s->tuned_tb = tb;
             } else {

@@ -1,16 +1,24 @@
 // Batched execution and the fusion-width / tile-size autotuner.
 //
-// msv_batch_run keeps one compressed device store per circuit and runs pass
-// level l of every circuit that has one in a single launch (one launch per
-// level and tile size): the circuits' tiles together fill the GPU even when
-// each circuit alone is small.
+// msv_batch_run keeps one compressed device store per circuit and runs every
+// pass of every circuit in ONE launch of persistent workgroups
+// (batch_kernel.hip): work items are (circuit, pass level, tile), taken in
+// level-major order from a device queue; a tile of level l waits until its
+// circuit's level l - 1 is complete (per-circuit completion counters). Small
+// circuits thus fill the GPU together, and nothing returns to the host
+// between levels.
 //
-// The autotuner picks, per circuit, the fusion width k (1..5) and the tile
-// size 2^tb (tb 10..12) that minimise a cost model over the circuit's plan:
+// The autotuner picks the fusion width k (1..5) per circuit, and the tile
+// size 2^tb (one per batch, since a launch is compiled for one tile size;
+// per circuit for single simulators), that minimise a cost model over the
+// circuit's plan:
 //   sum over passes of 2^n * (c_pass[tb] + sum over ops c_op[type][k]).
-// The per-amplitude coefficients are measured once per process on the GPU
-// with timed passes of a fixed synthetic state (n = 20): an empty pass per
-// tile size, and passes of 8 identical ops per op kind and width.
+// By default the coefficients are a fixed table measured on an MI355X with
+// msv_autotune_calibrate (so plans, and with them compressed results, are the
+// same in every process; ties go to the smaller tb, then the smaller k).
+// Autotune mode 2 measures them in the current process instead: timed passes
+// of a fixed synthetic state (n = 20), an empty pass per tile size and passes
+// of 8 identical ops per op kind and width.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -33,7 +41,34 @@ struct CostModel {
     double diag = 0, phase = 0;
 };
 
-CostModel g_cost[2];   // [is_double]
+// Fixed coefficients (ns per amplitude), measured on an MI355X by
+// msv_autotune_calibrate; index [is_double].
+CostModel fixed_model(bool is_double)
+{
+    CostModel m;
+    m.ready = true;
+    if (is_double) {
+        const double pass[14] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0.015486, 0.015256, 0.019796, 0};
+        const double dense[6] = {0, 0.0029368, 0.0033087, 0.0072421, 0.0106653, 0.0310950};
+        std::copy(pass, pass + 14, m.pass);
+        std::copy(dense, dense + 6, m.dense);
+        m.diag = 0.0;
+        m.phase = 0.00054348;
+    } else {
+        const double pass[14] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0.014341, 0.015753, 0.019834, 0};
+        const double dense[6] = {0, 0.0027701, 0.0029894, 0.0048918, 0.0061219, 0.0173832};
+        std::copy(pass, pass + 14, m.pass);
+        std::copy(dense, dense + 6, m.dense);
+        m.diag = 0.0;
+        m.phase = 0.0;
+    }
+    // tile sizes 8 and 9 (batches with small circuits) cost like 10 plus the
+    // extra passes they imply
+    m.pass[8] = m.pass[9] = m.pass[10];
+    return m;
+}
+
+CostModel g_live[2];   // [is_double], measured once per process (mode 2)
 std::mutex g_cost_mu;
 
 // Time passes of `reps` identical gates on a fresh 20-qubit compressed state.
@@ -55,11 +90,8 @@ int time_pass(msv_sim *s, const std::vector<msv_gate> &gates, double *sec)
     return MSV_OK;
 }
 
-int calibrate(bool is_double, hipStream_t stream)
+int measure_model(bool is_double, hipStream_t stream, CostModel &cm)
 {
-    std::lock_guard<std::mutex> lk(g_cost_mu);
-    CostModel &cm = g_cost[is_double];
-    if (cm.ready) return MSV_OK;
     const int n = 20;
     const double N = (double)(1u << n);
     msv_sim *s = nullptr;
@@ -79,6 +111,7 @@ int calibrate(bool is_double, hipStream_t stream)
         if ((st = time_pass(s, g, &t))) return st;
         cm.pass[tb] = t * 1e9 / N;
     }
+    cm.pass[8] = cm.pass[9] = cm.pass[10];
     if ((st = msv_set_option(s, "tile_qubits", 12))) return st;
     const double base = cm.pass[12];
     // dense ops of width k on qubits 6..6+k-1 (all inside the tile), 8 in a row
@@ -120,6 +153,23 @@ int calibrate(bool is_double, hipStream_t stream)
     return MSV_OK;
 }
 
+// The model of autotune mode `mode` (1 fixed table, 2 measured in this process).
+int model_for(bool is_double, int mode, hipStream_t stream, CostModel *out)
+{
+    if (mode != 2) {
+        *out = fixed_model(is_double);
+        return MSV_OK;
+    }
+    std::lock_guard<std::mutex> lk(g_cost_mu);
+    CostModel &cm = g_live[is_double];
+    if (!cm.ready) {
+        int st = measure_model(is_double, stream, cm);
+        if (st) return st;
+    }
+    *out = cm;
+    return MSV_OK;
+}
+
 double predict(const CostModel &cm, const std::vector<Pass> &passes, int n, int tb)
 {
     double c = 0.0;
@@ -134,30 +184,47 @@ double predict(const CostModel &cm, const std::vector<Pass> &passes, int n, int 
     return c * std::ldexp(1.0, n);
 }
 
+
+// Best fusion width for a circuit at tile size tb: (k, predicted cost, plan).
+double best_k_at(const CostModel &cm, const std::vector<Prim> &prims, int n, int tb, int *k_out,
+                 std::vector<Pass> *out)
+{
+    double best = 1e300;
+    for (int k = 1; k <= kMaxFuse; ++k) {
+        PlanOptions o;
+        o.n = n;
+        o.tb = tb;
+        o.k_max = k;
+        std::vector<Pass> ps = plan_passes(prims, o);
+        const double c = predict(cm, ps, n, std::max(tb, 8));
+        if (c < best) {   // strict: ties keep the smaller k
+            best = c;
+            *k_out = k;
+            if (out) *out = std::move(ps);
+        }
+    }
+    return best;
+}
+
 }  // namespace
 
 // Choose (k_max, tb) for a circuit; returns the chosen plan in *out.
-int autotune(bool is_double, hipStream_t stream, const std::vector<Prim> &prims, int n, int *k_out, int *tb_out,
-             std::vector<Pass> *out)
+int autotune(bool is_double, int mode, hipStream_t stream, const std::vector<Prim> &prims, int n, int *k_out,
+             int *tb_out, std::vector<Pass> *out)
 {
+    CostModel cm;
     int st;
-    if ((st = calibrate(is_double, stream))) return st;
-    const CostModel &cm = g_cost[is_double];
+    if ((st = model_for(is_double, mode, stream, &cm))) return st;
     double best = 1e300;
     for (int tb = std::min(n, 10); tb <= std::min(n, 12); ++tb) {
-        for (int k = 1; k <= kMaxFuse; ++k) {
-            PlanOptions o;
-            o.n = n;
-            o.tb = tb;
-            o.k_max = k;
-            std::vector<Pass> ps = plan_passes(prims, o);
-            const double c = predict(cm, ps, n, std::max(tb, 10));
-            if (c < best) {
-                best = c;
-                *k_out = k;
-                *tb_out = tb;
-                if (out) *out = ps;
-            }
+        int k = 1;
+        std::vector<Pass> ps;
+        const double c = best_k_at(cm, prims, n, tb, &k, &ps);
+        if (c < best) {   // strict: ties keep the smaller tb
+            best = c;
+            *k_out = k;
+            *tb_out = tb;
+            if (out) *out = std::move(ps);
         }
     }
     return MSV_OK;
@@ -253,33 +320,60 @@ extern "C" int msv_batch_run(const msv_circuit *circuits, size_t count, int dtyp
         if ((st = msv_set_chunk_qubits(s, std::min(c.n_qubits, 20)))) return st;
         if ((st = msv_init_basis(s, c.init_basis))) return st;
     }
-    // plans: the cost-model search runs on the host, circuits in parallel
-    if (tune && (st = calibrate(dbl, stream))) return st;
+    // plans: one tile size for the whole batch (a launch is compiled for one),
+    // the fusion width per circuit; the cost-model search runs on the host,
+    // circuits in parallel
+    int min_n = 64;
+    for (size_t i = 0; i < count; ++i) min_n = std::min(min_n, circuits[i].n_qubits);
+    int tb_batch = 12;
     {
         const unsigned nt = std::max(1u, std::min<unsigned>(16, std::thread::hardware_concurrency()));
-        std::vector<int> status(count, MSV_OK);
-        auto work = [&](unsigned t) {
-            for (size_t i = t; i < count; i += nt) {
-                const int nq = circuits[i].n_qubits;
-                if (tune) {
-                    status[i] = autotune(dbl, stream, prims[i], nq, &ks[i], &tbs[i], &plans[i]);
-                } else {
-                    PlanOptions o;
-                    o.n = nq;
-                    o.k_max = std::max(1, std::min(5, opts->k_max));
-                    o.tb = opts->log2_tile ? std::min(std::max(opts->log2_tile, 8), std::min(12, nq)) : std::min(12, nq);
-                    ks[i] = o.k_max;
-                    tbs[i] = o.tb;
-                    plans[i] = plan_passes(prims[i], o);
+        auto parallel = [&](auto &&fn) {
+            std::vector<std::thread> pool;
+            for (unsigned t = 1; t < nt; ++t) pool.emplace_back(fn, t, nt);
+            fn(0u, nt);
+            for (auto &th : pool) th.join();
+        };
+        if (tune) {
+            CostModel cm;
+            if ((st = model_for(dbl, opts ? opts->autotune : 1, stream, &cm))) return st;
+            std::vector<int> cand;
+            for (int tb = std::min(10, min_n); tb <= std::min(12, min_n); ++tb) cand.push_back(tb);
+            const size_t nc = cand.size();
+            std::vector<double> cost(count * nc);
+            std::vector<int> kk(count * nc, 1);
+            parallel([&](unsigned t, unsigned step) {
+                for (size_t i = t; i < count; i += step)
+                    for (size_t c = 0; c < nc; ++c)
+                        cost[i * nc + c] = best_k_at(cm, prims[i], circuits[i].n_qubits, cand[c], &kk[i * nc + c],
+                                                     nullptr);
+            });
+            double best = 1e300;
+            size_t cb = 0;
+            for (size_t c = 0; c < nc; ++c) {
+                double tot = 0.0;
+                for (size_t i = 0; i < count; ++i) tot += cost[i * nc + c];
+                if (tot < best) {   // strict: ties keep the smaller tile
+                    best = tot;
+                    cb = c;
                 }
             }
-        };
-        std::vector<std::thread> pool;
-        for (unsigned t = 1; t < nt; ++t) pool.emplace_back(work, t);
-        work(0);
-        for (auto &th : pool) th.join();
-        for (size_t i = 0; i < count; ++i)
-            if (status[i] != MSV_OK) return status[i];
+            tb_batch = cand[cb];
+            for (size_t i = 0; i < count; ++i) ks[i] = kk[i * nc + cb];
+        } else {
+            tb_batch = opts->log2_tile ? std::min(std::max(opts->log2_tile, 8), std::min(12, min_n)) : std::min(12, min_n);
+            for (size_t i = 0; i < count; ++i) ks[i] = std::max(1, std::min(5, opts->k_max));
+        }
+        for (size_t i = 0; i < count; ++i) tbs[i] = tb_batch;
+        parallel([&](unsigned t, unsigned step) {
+            for (size_t i = t; i < count; i += step) {
+                PlanOptions o;
+                o.n = circuits[i].n_qubits;
+                o.tb = tb_batch;
+                o.k_max = ks[i];
+                plans[i] = plan_passes(prims[i], o);
+            }
+        });
     }
     // lower every circuit's plan into one op buffer and one pool
     std::vector<OpDesc> ops;
@@ -311,50 +405,44 @@ extern "C" int msv_batch_run(const msv_circuit *circuits, size_t count, int dtyp
         fused += oi.size();
         total_gates += circuits[i].n_gates;
     }
-    // items, level by level and tile size by tile size; states ping-pong
-    std::vector<BatchItem> items;
-    std::vector<uint64_t> prefix;
-    struct Launch { int tb; size_t first, count; uint64_t tiles; size_t prefix0; int max_k; };
-    std::vector<Launch> launches;
+    // descriptors, level-major (the queue order); states ping-pong
+    std::vector<BatchDesc> descs;
+    std::vector<uint64_t> prefix, part_off;
     std::vector<int> cur(count, 0);
-    std::vector<uint64_t> part_off;   // per item: first per-tile triple
-    uint64_t part_total = 0;
+    std::vector<uint64_t> tiles_before(count, 0);
+    uint64_t n_items = 0, part_total = 0;
+    int max_k = 0;
     for (size_t l = 0; l < max_levels; ++l) {
-        for (int tb = 8; tb <= 12; ++tb) {
-            Launch L{tb, items.size(), 0, 0, prefix.size(), 0};
-            uint64_t acc = 0;
-            for (size_t i = 0; i < count; ++i) {
-                if (tbs[i] != tb || l >= geoms[i].size()) continue;
-                msv_sim *s = sims.v[i];
-                BatchItem it{};
-                it.geo = geoms[i][l];
-                L.max_k = std::max(L.max_k, (int)it.geo.max_k);
-                it.buf.in = s->st[cur[i]].view();
-                it.buf.out = s->st[cur[i] ^ 1].view();
-                it.buf.inv_step = s->inv_step();
-                it.buf.step = s->step();
-                it.buf.scale = 1.0;
-                it.buf.check_err = 1;
-                it.buf.slot_tile0 = 0;
-                part_off.push_back(part_total);
-                part_total += it.geo.n_tiles;
-                items.push_back(it);
-                prefix.push_back(acc);
-                acc += it.geo.n_tiles;
-                cur[i] ^= 1;
-            }
-            L.count = items.size() - L.first;
-            L.tiles = acc;
-            if (L.count) launches.push_back(L);
+        for (size_t i = 0; i < count; ++i) {
+            if (l >= geoms[i].size()) continue;
+            msv_sim *s = sims.v[i];
+            BatchDesc d{};
+            d.geo = geoms[i][l];
+            max_k = std::max(max_k, (int)d.geo.max_k);
+            d.buf.in = s->st[cur[i]].view();
+            d.buf.out = s->st[cur[i] ^ 1].view();
+            d.buf.inv_step = s->inv_step();
+            d.buf.step = s->step();
+            d.buf.scale = 1.0;
+            d.buf.check_err = 1;
+            d.buf.slot_tile0 = 0;
+            d.circuit = (uint32_t)i;
+            d.need = tiles_before[i];
+            tiles_before[i] += d.geo.n_tiles;
+            part_off.push_back(part_total);
+            part_total += d.geo.n_tiles;
+            prefix.push_back(n_items);
+            n_items += d.geo.n_tiles;
+            descs.push_back(d);
+            cur[i] ^= 1;
         }
     }
-    // device buffers: ops, pool, items, prefixes, partials, flags, stats
-    DevMem d_ops, d_pool, d_items, d_prefix, d_part, d_flags, d_off, d_stats;
+    // device buffers: ops, pool, descriptors, prefixes, partials, flags, stats, queue
+    DevMem d_ops, d_pool, d_descs, d_prefix, d_part, d_flags, d_off, d_stats, d_queue;
     struct FreeAll {
-        msv_sim *any;
         std::vector<DevMem *> m;
         ~FreeAll() { for (auto *x : m) if (x->p) (void)hipFree(x->p); }
-    } fa{nullptr, {&d_ops, &d_pool, &d_items, &d_prefix, &d_part, &d_flags, &d_off, &d_stats}};
+    } fa{{&d_ops, &d_pool, &d_descs, &d_prefix, &d_part, &d_flags, &d_off, &d_stats, &d_queue}};
     auto dalloc = [&](DevMem &m, size_t b) -> int {
         if (hipMalloc(&m.p, std::max<size_t>(b, 256)) != hipSuccess) {
             (void)hipGetLastError();
@@ -365,19 +453,21 @@ extern "C" int msv_batch_run(const msv_circuit *circuits, size_t count, int dtyp
         return MSV_OK;
     };
     const size_t pool_bytes = dbl ? pd.size() * 8 : pf.size() * 4;
+    const size_t queue_bytes = 256 + 4 * count;   // head (8 bytes), then done[count]
     if ((st = dalloc(d_ops, ops.size() * sizeof(OpDesc))) || (st = dalloc(d_pool, pool_bytes)) ||
-        (st = dalloc(d_items, items.size() * sizeof(BatchItem))) || (st = dalloc(d_prefix, 8 * prefix.size())) ||
+        (st = dalloc(d_descs, descs.size() * sizeof(BatchDesc))) || (st = dalloc(d_prefix, 8 * prefix.size())) ||
         (st = dalloc(d_part, 24 * part_total)) || (st = dalloc(d_flags, 256)) ||
-        (st = dalloc(d_off, 8 * (items.size() + 1))) || (st = dalloc(d_stats, 24 * items.size())))
+        (st = dalloc(d_off, 8 * (descs.size() + 1))) || (st = dalloc(d_stats, 24 * descs.size())) ||
+        (st = dalloc(d_queue, queue_bytes)))
         return st;
-    for (size_t j = 0; j < items.size(); ++j) {
-        items[j].buf.ops = (const OpDesc *)d_ops.p;
-        items[j].buf.pool = d_pool.p;
-        items[j].buf.flags = (uint32_t *)d_flags.p;
-        items[j].buf.part = (double *)d_part.p + 3 * part_off[j];
+    for (size_t j = 0; j < descs.size(); ++j) {
+        descs[j].buf.ops = (const OpDesc *)d_ops.p;
+        descs[j].buf.pool = d_pool.p;
+        descs[j].buf.flags = (uint32_t *)d_flags.p;
+        descs[j].buf.part = (double *)d_part.p + 3 * part_off[j];
     }
-    std::vector<uint64_t> offs(items.size() + 1, 0);
-    for (size_t j = 0; j < items.size(); ++j) offs[j + 1] = part_off[j] + items[j].geo.n_tiles;
+    std::vector<uint64_t> offs(descs.size() + 1, 0);
+    for (size_t j = 0; j < descs.size(); ++j) offs[j + 1] = part_off[j] + descs[j].geo.n_tiles;
     auto h2d = [&](void *dst, const void *src, size_t b) -> int {
         if (b && hipMemcpy(dst, src, b, hipMemcpyHostToDevice) != hipSuccess)
             return hip_fail(nullptr, hipErrorInvalidValue, "batch upload");
@@ -385,27 +475,37 @@ extern "C" int msv_batch_run(const msv_circuit *circuits, size_t count, int dtyp
     };
     if ((st = h2d(d_ops.p, ops.data(), ops.size() * sizeof(OpDesc))) ||
         (st = h2d(d_pool.p, dbl ? (const void *)pd.data() : (const void *)pf.data(), pool_bytes)) ||
-        (st = h2d(d_items.p, items.data(), items.size() * sizeof(BatchItem))) ||
+        (st = h2d(d_descs.p, descs.data(), descs.size() * sizeof(BatchDesc))) ||
         (st = h2d(d_prefix.p, prefix.data(), 8 * prefix.size())) || (st = h2d(d_off.p, offs.data(), 8 * offs.size())))
         return st;
-    if (hipMemsetAsync(d_flags.p, 0, 16, stream) != hipSuccess) return hip_fail(nullptr, hipErrorUnknown, "memset");
+    if (hipMemsetAsync(d_flags.p, 0, 16, stream) != hipSuccess ||
+        hipMemsetAsync(d_queue.p, 0, queue_bytes, stream) != hipSuccess)
+        return hip_fail(nullptr, hipErrorUnknown, "memset");
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail_global(MSV_E_DEVICE, "event creation failed");
     struct EG { hipEvent_t a, b; ~EG() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } eg{e0, e1};
     (void)hipEventRecord(e0, stream);
-    for (const Launch &L : launches) {
-        hipError_t e = launch_batch_pass(dbl, L.tb, L.max_k, (const BatchItem *)d_items.p + L.first,
-                                         (const uint64_t *)d_prefix.p + L.prefix0, (int)L.count, L.tiles, stream);
-        if (e != hipSuccess) return hip_fail(nullptr, e, "launch_batch_pass");
+    int grid = 0;
+    {
+        // a dependency wait of more than 2^22 polls (a few seconds; a level
+        // normally completes in well under a millisecond) means something is
+        // wrong: the kernel then leaves the queue
+        const uint64_t spin_limit = 1ull << 22;
+        hipError_t e = launch_batch_persistent(dbl, tb_batch, max_k, (const BatchDesc *)d_descs.p,
+                                               (const uint64_t *)d_prefix.p, (int)descs.size(), n_items,
+                                               (unsigned long long *)d_queue.p,
+                                               (unsigned int *)((uint8_t *)d_queue.p + 256), (uint32_t *)d_flags.p,
+                                               spin_limit, &grid, stream);
+        if (e != hipSuccess) return hip_fail(nullptr, e, "launch_batch_persistent");
     }
     (void)hipEventRecord(e1, stream);
-    if (launch_pass_stats((const double *)d_part.p, (const uint64_t *)d_off.p, (int)items.size(),
+    if (launch_pass_stats((const double *)d_part.p, (const uint64_t *)d_off.p, (int)descs.size(),
                           (double *)d_stats.p, stream) != hipSuccess)
         return hip_fail(nullptr, hipErrorUnknown, "pass stats");
-    std::vector<double> hs(3 * items.size() + 3, 0.0);
+    std::vector<double> hs(3 * descs.size() + 3, 0.0);
     uint32_t flags = 0;
-    if (hipMemcpyAsync(hs.data(), d_stats.p, 24 * items.size(), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+    if (hipMemcpyAsync(hs.data(), d_stats.p, 24 * descs.size(), hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipMemcpyAsync(&flags, d_flags.p, 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess)
         return hip_fail(nullptr, hipErrorUnknown, "batch readback");
@@ -414,34 +514,28 @@ extern "C" int msv_batch_run(const msv_circuit *circuits, size_t count, int dtyp
     // hand each simulator its final store so read-out sees it
     for (size_t i = 0; i < count; ++i) sims.v[i]->cur = cur[i];
     msv_stats agg{};
-    agg.passes = items.size();
+    agg.passes = descs.size();
     agg.gates = total_gates;
     agg.fused_ops = fused;
     agg.t_kernel = ms * 1e-3;
     agg.t_pass = ms * 1e-3;
-    agg.kernel_launches = launches.size();
-    uint64_t words = 0;
-    for (size_t j = 0; j < items.size(); ++j) {
+    agg.kernel_launches = 1;
+    for (size_t j = 0; j < descs.size(); ++j) {
         agg.max_err_all = std::max(agg.max_err_all, hs[3 * j + 1]);
         // the bound of the item's circuit (same eb for all; x <= sqrt(norm2))
         const double uT = dbl ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
         const double xmax = std::max(1.0, std::sqrt(std::max(hs[3 * j], 0.0)));
         if (hs[3 * j + 1] > eb * (1.0 + std::ldexp(1.0, -20)) + 2.0 * uT * std::max(xmax, eb))
             ++agg.bound_violations;
-        (void)words;
     }
     agg.err_bound = eb * (1.0 + std::ldexp(1.0, -20)) + 2.0 * (dbl ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24));
-    // final compressed size, from each circuit's last pass
-    for (size_t i = 0; i < count; ++i) {
-        const uint64_t nblk = 2ull << (circuits[i].n_qubits - 6);
-        agg.uncompressed_bytes += (uint64_t)(dbl ? 16 : 8) << circuits[i].n_qubits;
-        agg.pass_bytes += 0;
-        (void)nblk;
-    }
-    for (size_t j = 0; j < items.size(); ++j) {
-        const uint64_t nblk = 2ull << (items[j].geo.n - 6);
+    for (size_t i = 0; i < count; ++i) agg.uncompressed_bytes += (uint64_t)(dbl ? 16 : 8) << circuits[i].n_qubits;
+    for (size_t j = 0; j < descs.size(); ++j) {
+        const uint64_t nblk = 2ull << (descs[j].geo.n - 6);
         agg.pass_bytes += 18 * nblk + (uint64_t)(16.0 * hs[3 * j + 2]);   // in ~ out payload
     }
+    if (flags & kFlagQueueTimeout)
+        return fail_global(MSV_E_DEVICE, "batched launch: a dependency wait exceeded its limit");
     if (flags & 1u) return fail_global(MSV_E_RANGE, "a value left the codec range in a batched circuit");
     if (amps_out)
         for (size_t i = 0; i < count; ++i)
@@ -484,5 +578,19 @@ extern "C" int msv_batch_adjoint(const msv_circuit *ansatz, const double *params
     for (auto &th : pool) th.join();
     for (size_t w = 0; w < nw; ++w)
         if (status[w] != MSV_OK) return fail_global(status[w], msg[w].c_str());
+    return MSV_OK;
+}
+
+extern "C" int msv_autotune_calibrate(int dtype, double *model, size_t cap)
+{
+    if ((dtype != MSV_C128 && dtype != MSV_C64) || !model || cap < 10)
+        return fail_global(MSV_E_ARG, "msv_autotune_calibrate: bad argument");
+    CostModel cm;
+    int st = measure_model(dtype == MSV_C128, nullptr, cm);
+    if (st) return st;
+    for (int tb = 10; tb <= 12; ++tb) model[tb - 10] = cm.pass[tb];
+    for (int k = 1; k <= 5; ++k) model[2 + k] = cm.dense[k];
+    model[8] = cm.diag;
+    model[9] = cm.phase;
     return MSV_OK;
 }

@@ -27,9 +27,10 @@ int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOpt
 // Lower passes for the state's real type.
 void lower_for(const msv_sim *s, const std::vector<Pass> &passes, const PlanOptions &o, Lowered &low);
 
-// Autotuner: fusion width and tile size minimising the calibrated cost model.
-int autotune(bool is_double, hipStream_t stream, const std::vector<Prim> &prims, int n, int *k_out, int *tb_out,
-             std::vector<Pass> *out);
+// Autotuner: fusion width and tile size minimising the cost model of `mode`
+// (1 fixed table, 2 measured in this process).
+int autotune(bool is_double, int mode, hipStream_t stream, const std::vector<Prim> &prims, int n, int *k_out,
+             int *tb_out, std::vector<Pass> *out);
 
 // Host store (compressed chunks in pinned host memory).
 int apply_host_store(msv_sim *s, const std::vector<Prim> &prims, size_t n_gates);

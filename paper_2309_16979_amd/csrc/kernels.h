@@ -48,20 +48,37 @@ struct AdjointBuffers {
     uint64_t grad_stride;
 };
 
-// One (circuit or parameter set, pass) of a batched launch. The item's
-// workgroups cover tiles [geo.tile_begin, geo.tile_begin + geo.n_tiles); its
-// per-tile statistics go to buf.part[3 * local tile].
-struct BatchItem {
+// One (circuit, pass level) of a batched launch: its tiles
+// [geo.tile_begin, geo.tile_begin + geo.n_tiles) are work items; per-tile
+// statistics go to buf.part[3 * local tile]. Its tiles may start once
+// done[circuit] >= need: need counts the tiles of the circuit's earlier
+// levels, which wrote the store this level reads.
+struct BatchDesc {
     PassGeom geo;
     PassBuffers buf;
+    uint32_t circuit;
+    uint32_t pad_;
+    uint64_t need;
 };
 
-// Run every item's pass in one launch of sum(n_tiles) workgroups (max_k: the
-// widest dense op of any item, selects the kernel variant);
-// prefix[i] = first workgroup of item i (prefix[0] = 0). All items share tb
-// and the compressed device layout.
-hipError_t launch_batch_pass(bool is_double, int tb, int max_k, const BatchItem *items, const uint64_t *prefix,
-                             int n_items, uint64_t total_tiles, hipStream_t stream);
+// Flags bit of a batched launch whose dependency wait exceeded its limit
+// (every workgroup then leaves the queue; the results are not usable).
+constexpr uint32_t kFlagQueueTimeout = 16u;
+
+// All tiles of all descriptors in ONE launch of persistent workgroups (as
+// many as fit on the device at once, at most the item count). Work items are
+// numbered level-major (descriptor order, then tile): item i belongs to the
+// descriptor d with prefix[d] <= i < prefix[d + 1]. A workgroup takes the next
+// item with an atomic add on *head, waits (one thread, bounded by spin_limit
+// sleeps) until done[circuit] reaches the descriptor's need, runs the tile,
+// and adds 1 to done[circuit] after a device-scope fence. Items only wait on
+// items taken before them, so the queue always drains. *head and done[] must
+// be zero before the launch. All descriptors share tb and the compressed
+// layout; max_k (widest dense op) selects the kernel variant. *grid receives
+// the number of workgroups launched.
+hipError_t launch_batch_persistent(bool is_double, int tb, int max_k, const BatchDesc *descs, const uint64_t *prefix,
+                                   int n_desc, uint64_t n_items, unsigned long long *head, unsigned int *done,
+                                   uint32_t *flags, uint64_t spin_limit, int *grid, hipStream_t stream);
 
 hipError_t launch_adjoint_pass(bool is_double, bool compressed, const PassGeom &geo, const AdjointBuffers &buf,
                                hipStream_t stream);

@@ -306,8 +306,10 @@ def plan(n: int, gates: Sequence, log2_tile: int = 12, k_max: int = 2, lookahead
 
 def batch_run(circuits, dtype: str = "c64", eb: float = 1e-4, autotune: bool = True, k_max: int = 2,
               log2_tile: int = 0, mma: str = "f32", want_amplitudes: bool = False):
-    """Run many circuits, each given as (n, gates, init_basis), with one launch
-    per pass level. Returns (stats dict, list of amplitude arrays or None)."""
+    """Run many circuits, each given as (n, gates, init_basis), in one
+    persistent launch. autotune: 0/False = k_max and log2_tile as given,
+    1/True = fixed cost model, 2 = model measured in this process. Returns
+    (stats dict, list of amplitude arrays or None)."""
     Lb = load()
     arrs, keeps = [], []
     cs = (L.Circuit * len(circuits))()
@@ -316,7 +318,7 @@ def batch_run(circuits, dtype: str = "c64", eb: float = 1e-4, autotune: bool = T
         arrs.append(arr)
         keeps.append(keep)
         cs[i] = L.Circuit(n, arr, len(gates), int(x))
-    opts = L.BatchOpts(1 if autotune else 0, k_max, log2_tile, _MMA[mma])
+    opts = L.BatchOpts(int(autotune), k_max, log2_tile, _MMA[mma])
     npdt = np.complex128 if _DT[dtype] == L.C128 else np.complex64
     outs = [np.empty(1 << n, dtype=npdt) for n, _, _ in circuits] if want_amplitudes else None
     ptrs = (C.c_void_p * len(circuits))(*[o.ctypes.data for o in outs]) if outs else None
@@ -443,3 +445,11 @@ def probe_transfer(n: int, strategy: str, to_device: bool, pinned: bool, max_cal
     check(Lb.msv_probe_transfer(n, XFER_STRATEGIES[strategy], int(bool(to_device)), int(bool(pinned)), max_calls,
                                 C.byref(sec), C.byref(per), C.byref(calls)))
     return {"seconds": sec.value, "per_call_s": per.value, "calls": calls.value}
+
+
+def autotune_calibrate(dtype: str = "c64") -> dict:
+    """Measure the autotuner's cost model on this device (ns per amplitude)."""
+    m = np.zeros(10)
+    check(load().msv_autotune_calibrate(_DT[dtype], m.ctypes.data, m.size))
+    return {"pass_tb10": m[0], "pass_tb11": m[1], "pass_tb12": m[2],
+            "dense": {k: m[2 + k] for k in range(1, 6)}, "diag": m[8], "phase": m[9]}

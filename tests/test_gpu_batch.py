@@ -59,3 +59,34 @@ def test_batch_adjoint_matches_single_adjoint():
         ref = oracle.param_shift_gradient(n, gates, P[k], masks, coeffs)
         assert np.max(np.abs(gr[k] - ref)) < 1e-10
         assert ev[k] == pytest.approx(oracle.energy(n, gates, P[k], masks, coeffs), abs=1e-12)
+
+
+def test_batch_is_one_persistent_launch_and_deterministic_across_processes():
+    """The whole batch (every pass of every circuit) is one launch, and the
+    autotuned plan, hence every output byte, is the same in two fresh
+    processes (fixed cost model)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = r'''
+import hashlib, sys
+sys.path.insert(0, %r)
+from paper_2309_16979_amd import batch_run
+from workloads import batch_circuits
+circs = batch_circuits(20, seed=11, n_lo=12, n_hi=18, d_lo=10, d_hi=30)
+st, outs = batch_run([(n, g, 0) for n, g in circs], eb=1e-5, autotune=1, want_amplitudes=True)
+h = hashlib.sha256()
+for a in outs:
+    h.update(a.tobytes())
+print(st["kernel_launches"], st["passes"], h.hexdigest())
+''' % (root,)
+    res = []
+    for r in range(2):
+        log("batch process", r)
+        p = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+        assert p.returncode == 0, p.stderr[-2000:]
+        res.append(p.stdout.split()[-3:])
+    assert res[0] == res[1], res
+    assert res[0][0] == "1"
+    print("batch: launches %s, passes %s, digest %s" % tuple(res[0]))
