@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probes", action="store_true", help="skip the measured roofline denominators")
+    ap.add_argument("--cpu-share", type=float, default=0.0,
+                    help="host34: also run with this share of chunk groups on host cores")
     ap.add_argument("--no-extras", action="store_true", help="skip comparison runs outside the timed loop")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--workload", default="qft28",
@@ -423,12 +425,16 @@ def bench_host34(a):
         from paper_2309_16979_amd.msv import probe_denominators
         den = probe_denominators()
         out["denominators"] = den
-    for tag, eb, mode in (("eb_rel_0.1", 0.1, "rel"), ("eb_abs_1e-4", 1e-4, "abs")):
-        with Simulator(n, dtype="c64", eb=eb, eb_mode=mode, chunk_qubits=log2c, store="host", k_max=a.k) as s:
+    runs = [("eb_rel_0.1", 0.1, "rel", {}), ("eb_abs_1e-4", 1e-4, "abs", {})]
+    if a.cpu_share > 0:
+        runs.append(("eb_rel_0.1_cpu_share", 0.1, "rel", {"cpu_share": a.cpu_share, "cpu_threads": 8}))
+    for tag, eb, mode, opts in runs:
+        with Simulator(n, dtype="c64", eb=eb, eb_mode=mode, chunk_qubits=log2c, store="host", k_max=a.k,
+                       options=opts) as s:
             def run():
                 s.init_basis(0)
                 s.apply(gates)
-            reps = max(1, a.steps) if tag.startswith("eb_rel") else 1
+            reps = max(1, a.steps) if tag == "eb_rel_0.1" else 1
             dt, _ = _timed(run, reps)
             st = s.stats()
             link_bytes = st["h2d_bytes"] + st["d2h_bytes"]
@@ -439,6 +445,7 @@ def bench_host34(a):
                                "h2d_bytes": st["h2d_bytes"], "d2h_bytes": st["d2h_bytes"],
                                "overlap": st["overlap"], "t_kernel": st["t_kernel"], "t_total": st["t_total"],
                                "passes": st["passes"], "zero_groups_skipped": st["zero_groups_skipped"],
+                               "cpu_groups": st["cpu_groups"],
                                "link_GBps_over_apply": link_bytes / dt / 1e9},
                  "compression": {"ratio": st["ratio"], "compressed_bytes": st["compressed_bytes"],
                                  "reserved_bytes": st["reserved_bytes"], "max_err_all": st["max_err_all"],

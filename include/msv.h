@@ -121,6 +121,8 @@ typedef struct msv_stats {
                                     chunks were all ZERO; they stay ZERO under
                                     unitary ops, so they were neither staged nor
                                     run through the pass kernels                  */
+    uint64_t cpu_groups;         /* host store: chunk groups of the last apply run
+                                    on host cores (option "cpu_share")           */
 } msv_stats;
 
 typedef struct msv_sim msv_sim;  /* opaque, library-owned */
@@ -183,6 +185,12 @@ int msv_set_fusion(msv_sim *sim, int k_max, int mma_precision);
  *                  6 = never)
  *   "batch_chunks" host store: chunks per streamed batch (0 = automatic)
  *   "time_passes"  1 = time every pass kernel with events (msv_stats.t_pass)
+ *   "cpu_share"    host store: share (0..1, default 0) of each pass's non-ZERO
+ *                  chunk groups that host threads decode, update (FP64) and
+ *                  encode themselves while the GPU streams the rest (the
+ *                  paper's online-stage step (5)); those groups never cross
+ *                  the host link. Not with "renormalize".
+ *   "cpu_threads"  threads for it (0 = half the hardware threads)
  *   "lookahead"    gates the planner scans past a deferred gate to pull
  *                  commuting gates into the current pass (default 1024, 0 = none)
  *   "segments"     1 (default) = run runs of 1-2 qubit dense ops, diagonals and

@@ -36,7 +36,7 @@ class Stats(C.Structure):
         [("bound_violations", C.c_uint64), ("kernel_launches", C.c_uint64),
          ("t_pass", C.c_double), ("pass_bytes", C.c_uint64), ("mfma_ops", C.c_uint64),
          ("pass_valu_ops", C.c_double), ("pass_mfma_flops", C.c_double), ("pass_issue_ops", C.c_double),
-         ("zero_groups_skipped", C.c_uint64)]
+         ("zero_groups_skipped", C.c_uint64), ("cpu_groups", C.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -480,6 +480,12 @@ int msv_set_option(msv_sim *s, const char *key, double v)
     } else if (!strcmp(key, "autotune")) {
         if (v != iv || iv < 0 || iv > 2) return fail(s, MSV_E_ARG, "autotune in 0..2");
         s->autotune = iv;
+    } else if (!strcmp(key, "cpu_share")) {
+        if (!(v >= 0.0 && v <= 1.0)) return fail(s, MSV_E_ARG, "cpu_share in [0, 1]");
+        s->cpu_share = v;
+    } else if (!strcmp(key, "cpu_threads")) {
+        if (v != iv || iv < 0 || iv > 256) return fail(s, MSV_E_ARG, "cpu_threads in 0..256");
+        s->cpu_threads = iv;
     } else if (!strcmp(key, "time_passes")) {
         s->time_passes = v != 0.0;
     } else if (!strcmp(key, "batch_chunks")) {

@@ -15,9 +15,11 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <thread>
 
 #include "internal.h"
 
@@ -34,8 +36,10 @@ uint64_t chunk_bound(int log2c)
 }
 
 // Reserve `bytes` contiguous bytes in the arena; returns the position.
+// Serialised: host co-processing threads reserve space too.
 int arena_alloc(msv_sim *s, HostArena &a, uint64_t bytes, uint64_t *pos)
 {
+    std::lock_guard<std::mutex> lk(s->arena_mu);
     if (bytes > a.seg_bytes) return fail_sim(s, MSV_E_NOMEM, "batch larger than an arena segment");
     if (a.off + bytes > a.seg_bytes) {
         ++a.seg;
@@ -51,6 +55,15 @@ int arena_alloc(msv_sim *s, HostArena &a, uint64_t bytes, uint64_t *pos)
     a.off += align256(bytes);
     return MSV_OK;
 }
+
+}  // namespace
+
+int host_arena_alloc(msv_sim *s, int side, uint64_t bytes, uint64_t *pos)
+{
+    return arena_alloc(s, s->hs.arena[side], bytes, pos);
+}
+
+namespace {
 
 void arena_reset(HostArena &a)
 {
@@ -92,7 +105,13 @@ int setup(msv_sim *s)
             HIPCHK(s, hipEventCreate(e));
     }
     const uint64_t seg = std::max<uint64_t>(64ull << 20, align256(K * align256(cb)));
-    for (auto &a : h.arena) a.seg_bytes = seg;
+    for (auto &a : h.arena) {
+        a.seg_bytes = seg;
+        // segments are appended under the arena lock while other threads read
+        // through at(): the vector must never move (every allocation fits one
+        // segment, so a pass needs at most one segment per allocation)
+        a.segs.reserve(4 * n_chunks + 64);
+    }
     for (int i = 0; i < 2; ++i) {
         h.pos[i].assign(n_chunks, 0);
         h.bytes[i].assign(n_chunks, 0);
@@ -446,7 +465,11 @@ int apply_host_store(msv_sim *s, const std::vector<Prim> &prims, size_t n_gates)
     uint64_t h2d_bytes = 0, d2h_bytes = 0;
     double t_h2d = 0.0, t_d2h = 0.0, t_k = 0.0;
     const auto t0 = std::chrono::steady_clock::now();
-    uint64_t skipped = 0;
+    uint64_t skipped = 0, cpu_groups = 0;
+    if (s->renorm && s->cpu_share > 0.0)
+        return fail_sim(s, MSV_E_UNSUPPORTED, "host-core co-processing with renormalisation");
+    std::vector<double> cpu_norm(geoms.size(), 0.0), cpu_err(geoms.size(), 0.0), cpu_words(geoms.size(), 0.0);
+    bool cpu_bad = false;
     for (size_t p = 0; p < geoms.size(); ++p) {
         const PassPlan pp = pass_plan(s, geoms[p]);
         const int in_side = h.cur, out_side = h.cur ^ 1;
@@ -479,6 +502,42 @@ int apply_host_store(msv_sim *s, const std::vector<Prim> &prims, size_t n_gates)
             else
                 runs.push_back({g, g + 1});
         }
+        // host-core co-processing: the last cpu_share of the non-zero groups
+        // run on host threads while the GPU streams the others
+        std::vector<uint64_t> cpu_list;
+        if (s->cpu_share > 0.0) {
+            uint64_t nz = 0;
+            for (auto &r : runs) nz += r.second - r.first;
+            uint64_t want = (uint64_t)std::floor(s->cpu_share * (double)nz + 0.5);
+            while (want > 0 && !runs.empty()) {
+                auto &r = runs.back();
+                cpu_list.push_back(--r.second);
+                --want;
+                if (r.second == r.first) runs.pop_back();
+            }
+            cpu_groups += cpu_list.size();
+        }
+        std::atomic<size_t> next_cpu{0};
+        std::vector<std::thread> workers;
+        struct WorkerOut { double norm = 0, err = 0, words = 0; bool bad = false; int status = MSV_OK; };
+        const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+        const size_t nwk = cpu_list.empty() ? 0 : std::min<size_t>(cpu_list.size(),
+                                                  s->cpu_threads > 0 ? (size_t)s->cpu_threads : std::max(1u, hw / 2));
+        std::vector<WorkerOut> wout(nwk);
+        const double in_scale = p == 0 ? s->scale : 1.0;
+        for (size_t w = 0; w < nwk; ++w)
+            workers.emplace_back([&, w]() {
+                WorkerOut &o = wout[w];
+                for (size_t i = next_cpu++; i < cpu_list.size() && o.status == MSV_OK; i = next_cpu++) {
+                    const std::vector<uint64_t> gc = group_chunks(s, pp, cpu_list[i], cpu_list[i] + 1);
+                    o.status = cpu_group_pass(s, passes[p], gc, pp.Hq, in_side, out_side, in_scale, &o.norm, &o.err,
+                                              &o.words, &o.bad);
+                }
+            });
+        struct Join {
+            std::vector<std::thread> &t;
+            ~Join() { for (auto &x : t) if (x.joinable()) x.join(); }
+        } join{workers};
         // the statistics sum every tile's partials: skipped tiles contribute zeros
         HIPCHK(s, hipMemsetAsync(h.part.p, 0, 3 * 8 * tiles_per_pass, cs));
         const uint64_t n_batches = runs.size();
@@ -551,6 +610,14 @@ int apply_host_store(msv_sim *s, const std::vector<Prim> &prims, size_t n_gates)
             (st = finish_batch(s, h.bb[prev_set], prev_chunks, out_side, &d2h_bytes, h.tev[6 * prev_bi + 4],
                                h.tev[6 * prev_bi + 5])))
             return st;
+        for (auto &t : workers) t.join();
+        for (const WorkerOut &o : wout) {
+            if (o.status) return fail_sim(s, o.status, "host-core pass over a chunk group failed");
+            cpu_norm[p] += o.norm;
+            cpu_err[p] = std::max(cpu_err[p], o.err);
+            cpu_words[p] += o.words;
+            cpu_bad = cpu_bad || o.bad;
+        }
         HIPCHK(s, launch_pass_stats((const double *)h.part.p, (const uint64_t *)s->ws.pass_off.p, 1,
                                     (double *)s->ws.pass_stats.p + 3 * p, cs));
         HIPCHK(s, hipStreamSynchronize(h.d2h));
@@ -571,6 +638,13 @@ int apply_host_store(msv_sim *s, const std::vector<Prim> &prims, size_t n_gates)
         HIPCHK(s, hipMemcpy(hs.data(), s->ws.pass_stats.p, 8 * 3 * geoms.size(), hipMemcpyDeviceToHost));
     uint32_t f = 0;
     if ((st = read_flags(s, &f))) return st;
+    for (size_t p = 0; p < geoms.size(); ++p) {
+        hs[3 * p] += cpu_norm[p];
+        hs[3 * p + 1] = std::max(hs[3 * p + 1], cpu_err[p]);
+        hs[3 * p + 2] += cpu_words[p];
+    }
+    if (cpu_bad) f |= 1u;
+    s->stats.cpu_groups = cpu_groups;
     s->stats.passes = geoms.size();
     s->stats.fused_ops = ops.size();
     s->stats.zero_groups_skipped = skipped;

@@ -41,6 +41,15 @@ int host_store_decode_range(msv_sim *s, uint64_t first_amp, uint64_t count, void
 // a.amp_count), written from a.partials on; *groups receives their count.
 int host_store_reduce(msv_sim *s, ReduceArgs a, int *groups);
 void host_store_free(msv_sim *s);
+// Reserve `bytes` in the output arena of side `side` (thread-safe).
+int host_arena_alloc(msv_sim *s, int side, uint64_t bytes, uint64_t *pos);
+// Host-core co-processing: one pass over one chunk group on this thread
+// (decode, the pass's fused ops in FP64, encode into the output arena; the
+// chunk table of side out_side is updated). chunks in group order (crossing
+// qubits Hq counted up from chunks[0]). Adds the group's FP64 norm, max
+// error and payload words; *bad is set for a value out of the codec range.
+int cpu_group_pass(msv_sim *s, const Pass &pass, const std::vector<uint64_t> &chunks, const std::vector<int> &Hq,
+                   int in_side, int out_side, double scale, double *norm, double *err, double *words, bool *bad);
 
 }  // namespace msv
 

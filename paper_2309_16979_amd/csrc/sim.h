@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime_api.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -83,6 +84,8 @@ struct msv_sim {
     int batch_chunks = 0;
     int time_passes = 0;
     int autotune = 0;
+    double cpu_share = 0.0;          // host store: share of chunk groups run on host cores
+    int cpu_threads = 0;             // threads for them (0 = half the hardware threads)
     int lookahead = 1024;
     int segments = 1;                // register segments in pass kernels
     int relabel = 1;                 // SWAPs of block-index qubits as relabelling (compressed device store)
@@ -109,6 +112,7 @@ struct msv_sim {
     msv::DevStore lam[2];      // adjoint: lambda (compressed)
     int lcur = 0;
     msv::HostStore hs;         // host store
+    std::mutex arena_mu;       // host-store arena cursors (host co-processing threads write chunks too)
     msv::Workspace ws;
     double scale = 1.0;        // pending renormalisation factor, applied at decode
     msv_stats stats{};

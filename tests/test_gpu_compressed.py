@@ -245,3 +245,42 @@ def test_host_store_skips_zero_groups_bitwise():
     assert all(len(c) == 32 for c in ch_h[2:])
     assert st_h["zero_groups_skipped"] > 0 and st_h["passes"] == st_d["passes"]
     print("zero groups skipped:", st_h["zero_groups_skipped"], "passes", st_h["passes"])
+
+
+@pytest.mark.parametrize("dtype,eb,share", [("c64", 1e-5, 0.5), ("c128", 1e-7, 0.5), ("c64", 1e-5, 1.0)])
+def test_host_store_cpu_coprocessing(dtype, eb, share):
+    """Host-core co-processing (option cpu_share): host threads decode, update
+    and encode a share of each pass's chunk groups while the GPU streams the
+    rest. Every chunk, whoever wrote it, is a valid chunk of the format (the
+    oracle's decoder reads it to exactly the simulator's amplitudes), every
+    pass meets the bound, and the state matches the oracle within the
+    quantisation budget and the all-GPU run."""
+    from workloads import crossing_circuit
+    n, lc = 20, 14
+    gates = crossing_circuit(n, 12, lc, seed=6)
+    ref = oracle.simulate(n, gates, 0)
+    log("cpu share", dtype, eb, share)
+    with _sim(n, dtype, eb, chunk_qubits=lc, store="host", options={"cpu_share": share, "cpu_threads": 4}) as s:
+        s.init_basis(0)
+        s.apply(gates)
+        st = s.stats()
+        ps = s.pass_stats()
+        amps = s.amplitudes()
+        chunks = [s.export_chunk(c) for c in range(1 << (n - lc))]
+        fr, fn = s.fidelity(ref)
+    with _sim(n, dtype, eb, chunk_qubits=lc, store="host") as s0:
+        s0.init_basis(0)
+        s0.apply(gates)
+        a0 = s0.amplitudes()
+    assert st["cpu_groups"] > 0 and st["bound_violations"] == 0
+    assert np.all(ps[:, 1] <= st["err_bound"])
+    C = 1 << lc
+    for c, blob in enumerate(chunks):
+        dec = oracle.codec_decode(blob)
+        assert np.array_equal(dec.view(np.uint8), amps[c * C:(c + 1) * C].view(np.uint8)), c
+    P = st["passes"]
+    budget = 1.0 - 1.5 * P * (2.0 / 3.0) * (1 << n) * eb * eb
+    f_gpu = oracle.fidelity(a0, amps)[1]
+    print("cpu share %.1f %s: groups on host %d, F_norm %.8f (budget %.6f), F vs all-GPU %.8f"
+          % (share, dtype, st["cpu_groups"], fn, budget, f_gpu))
+    assert fn >= budget and f_gpu >= budget
