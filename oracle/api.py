@@ -137,8 +137,11 @@ def prob_one(psi: np.ndarray, q: int) -> float:
 
 
 def fidelity(ref: np.ndarray, psi: np.ndarray):
-    """(F_raw, F_norm): |<ref|psi>|^2 and the same over both squared norms."""
-    ov = np.vdot(ref.astype(np.complex128), psi.astype(np.complex128))
+    """(F_raw, F_norm): |<ref|psi>|^2 and the same over both squared norms,
+    every sum in FP64."""
+    ref = np.asarray(ref).astype(np.complex128)
+    psi = np.asarray(psi).astype(np.complex128)
+    ov = np.vdot(ref, psi)
     f_raw = float(abs(ov) ** 2)
     nn = float(np.vdot(psi, psi).real) * float(np.vdot(ref, ref).real)
     return f_raw, (f_raw / nn if nn > 0 else float("nan"))
