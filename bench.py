@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probes", action="store_true", help="skip the measured roofline denominators")
+    ap.add_argument("--torch-runtime", action="store_true",
+                    help="host34: run with PyTorch (and its copy of the HIP runtime) in the process")
     ap.add_argument("--cpu-share", type=float, default=0.0,
                     help="host34: also run with this share of chunk groups on host cores")
     ap.add_argument("--no-extras", action="store_true", help="skip comparison runs outside the timed loop")
@@ -192,6 +194,12 @@ def main():
               "(a state is not sharded across GPUs); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
+    if a.workload == "host34" and not a.torch_runtime:
+        # the library alone, on the HIP runtime it was built against: no
+        # PyTorch in the process (host-store runs need no torch memory)
+        os.environ["MSV_TORCH_RUNTIME"] = "0"
+        bench_host34(a)
+        return
     import torch
 
     from paper_2309_16979_amd import Simulator, _lib
@@ -353,12 +361,19 @@ def main():
 
 
 def _timed(fn, reps):
-    import torch
-    torch.cuda.synchronize()
+    """Wall time per call of fn (every library call returns with its work
+    finished; with torch in the process its queues are drained as well)."""
+    sync = None
+    if os.environ.get("MSV_TORCH_RUNTIME", "1") != "0":
+        import torch
+        sync = torch.cuda.synchronize
+    if sync:
+        sync()
     t0 = time.perf_counter()
     for _ in range(reps):
         r = fn()
-    torch.cuda.synchronize()
+    if sync:
+        sync()
     return (time.perf_counter() - t0) / reps, r
 
 
@@ -413,13 +428,14 @@ def bench_host34(a):
     keeps the state (the headline of this workload)."""
     from paper_2309_16979_amd import Simulator
     from workloads import crossing_circuit, ghz
+    use_torch = os.environ.get("MSV_TORCH_RUNTIME", "1") != "0"
     n, log2c = 34, 22
     gates = crossing_circuit(n, 40, log2c, seed=a.seed)
     out = {"metric": "amplitude-gate updates/sec incl. codec and host link", "unit": "amplitude-gate updates/s",
            "n_gpus": 1, "higher_is_better": True, "data": "synthetic: seeded random circuit, crossing 2q gates",
-           "dtype": "c64", "config": {"workload": "random depth 40, 30%% crossing 2q gates, n=34, complex64, "
+           "dtype": "c64", "config": {"workload": "random depth 40, 30% crossing 2q gates, n=34, complex64, "
                                       "chunk 2^22, host-pinned store; eb norm-relative 0.1 (and absolute 1e-4)",
-                                      "gates": len(gates)}}
+                                      "gates": len(gates), "pytorch_in_process": use_torch}}
     den = None
     if not a.no_probes:
         from paper_2309_16979_amd.msv import probe_denominators
@@ -430,7 +446,7 @@ def bench_host34(a):
         runs.append(("eb_rel_0.1_cpu_share", 0.1, "rel", {"cpu_share": a.cpu_share, "cpu_threads": 8}))
     for tag, eb, mode, opts in runs:
         with Simulator(n, dtype="c64", eb=eb, eb_mode=mode, chunk_qubits=log2c, store="host", k_max=a.k,
-                       options=opts) as s:
+                       options=opts, use_torch=use_torch) as s:
             def run():
                 s.init_basis(0)
                 s.apply(gates)
@@ -456,7 +472,7 @@ def bench_host34(a):
             out[tag] = r
             print("host34 %s: %.2f s per apply, ratio %.1f" % (tag, dt, st["ratio"]), file=sys.stderr, flush=True)
     out["value"] = out["eb_rel_0.1"]["updates_per_s"]
-    with Simulator(n, dtype="c64", eb=1e-4, chunk_qubits=log2c, store="host") as s:
+    with Simulator(n, dtype="c64", eb=1e-4, chunk_qubits=log2c, store="host", use_torch=use_torch) as s:
         s.init_basis(0)
         t0 = time.perf_counter()
         s.apply(ghz(n))

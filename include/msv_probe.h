@@ -37,7 +37,9 @@ int msv_probe_hbm_copy(size_t bytes, int reps, double *gbps);
  * and device memory with hipMemcpyAsync, `reps` (>= 1) times after one
  * warm-up, timed on the host around the synchronised copies.
  * direction: 0 host-to-device, 1 device-to-host, 2 both at once on two
- * streams (then *gbps counts the bytes of both directions). */
+ * streams (then *gbps counts the bytes of both directions), 3 device-to-host
+ * with the copy kind hipMemcpyDeviceToDeviceNoCU (a copy engine, no compute
+ * units; the pinned buffer is device-addressable). */
 int msv_probe_host_link(size_t bytes, int direction, int reps, double *gbps);
 
 /* Dense matrix-core throughput: 4 workgroups of 4 waves per compute unit,

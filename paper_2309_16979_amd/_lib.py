@@ -88,10 +88,13 @@ def load():
     # runtimes under the same sonames, and its libraries ask for them by an
     # unversioned name. Loading torch first makes libmsv bind to that copy;
     # loading libmsv first would put a second, competing runtime in the process.
-    try:
-        import torch  # noqa: F401
-    except ImportError:
-        pass
+    # MSV_TORCH_RUNTIME=0 keeps torch out: libmsv then runs on the HIP runtime
+    # it was built against (torch must then not be imported later on).
+    if os.environ.get("MSV_TORCH_RUNTIME", "1") != "0":
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
     L = C.CDLL(LIB_PATH)
     P = C.c_void_p
     sig = {

@@ -242,7 +242,7 @@ int msv_probe_hbm_copy(size_t bytes, int reps, double *gbps)
 
 int msv_probe_host_link(size_t bytes, int direction, int reps, double *gbps)
 {
-    if (!gbps || bytes < 4096 || reps < 1 || direction < 0 || direction > 2) return MSV_E_ARG;
+    if (!gbps || bytes < 4096 || reps < 1 || direction < 0 || direction > 3) return MSV_E_ARG;
     HipBuf h, d, h2, d2;
     h.host = h2.host = true;
     PCHK(hipHostMalloc(&h.p, bytes, hipHostMallocDefault));
@@ -260,6 +260,9 @@ int msv_probe_host_link(size_t bytes, int direction, int reps, double *gbps)
         for (int r = 0; r < rr; ++r) {
             if (direction == 0 || direction == 2) PCHK(hipMemcpyAsync(d.p, h.p, bytes, hipMemcpyHostToDevice, s0.s));
             if (direction == 1) PCHK(hipMemcpyAsync(h.p, d.p, bytes, hipMemcpyDeviceToHost, s0.s));
+            // the copy kind that keeps compute units out of it (a copy engine
+            // moves the bytes); pinned host memory is addressable by the device
+            if (direction == 3) PCHK(hipMemcpyAsync(h.p, d.p, bytes, hipMemcpyDeviceToDeviceNoCU, s0.s));
             if (direction == 2) PCHK(hipMemcpyAsync(h2.p, d2.p, bytes, hipMemcpyDeviceToHost, s1.s));
         }
         PCHK(hipStreamSynchronize(s0.s));

@@ -8,6 +8,7 @@ allocator hook) and the HIP stream (its current stream).
 from __future__ import annotations
 
 import ctypes as C
+import os
 from typing import Iterable, Optional, Sequence
 
 import numpy as np
@@ -112,6 +113,8 @@ class Simulator:
             check(self._L.msv_set_fusion(h, k_max, _MMA[mma]), h)
             for k, v in (options or {}).items():
                 check(self._L.msv_set_option(h, k.encode(), float(v)), h)
+            if use_torch is None and os.environ.get("MSV_TORCH_RUNTIME", "1") == "0":
+                use_torch = False
             if use_torch is None:
                 try:
                     import torch
