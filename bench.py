@@ -77,18 +77,20 @@ def parse():
     return ap.parse_args()
 
 
-DEVICE_SOURCES = ("codec_device.h", "device_ops.h", "kernels.h", "mfma_ops.h", "pass_kernel.h", "reg_ops.h",
-                  "tile_ops.h")
+# The complex64 compressed pass kernel that the counters in profiles/ cover:
+# its launcher, its instantiation and every header it includes.
+PASS_KERNEL_SOURCES = ("codec_device.h", "device_ops.h", "kernels.h", "mfma_ops.h", "pass_kernel.h", "reg_ops.h",
+                       "tile_ops.h", "pass_kernel.hip", "pass_f32.hip")
 
 
 def kernel_source_hash():
-    """Hash of the sources that make up the GPU kernels (.hip files and the
-    device headers); host-side planning code is not part of it."""
+    """Hash of the sources of the headline pass kernel (the files above);
+    other kernels and host-side planning code are not part of it."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2309_16979_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith(".hip") or f in DEVICE_SOURCES:
-            h.update(open(os.path.join(d, f), "rb").read())
+    for f in PASS_KERNEL_SOURCES:
+        h.update(f.encode())
+        h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
 
