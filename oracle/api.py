@@ -61,6 +61,9 @@ def lib():
         L.orc_codec_encode.argtypes = [C.c_int, C.c_int, C.c_double, C.c_void_p,
                                        C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]
         L.orc_codec_encode.restype = C.c_int
+        L.orc_codec_encode_mode.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_void_p,
+                                            C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]
+        L.orc_codec_encode_mode.restype = C.c_int
         L.orc_codec_decode.argtypes = [C.c_void_p, C.c_size_t, C.c_void_p]
         L.orc_codec_decode.restype = C.c_int
         L.orc_codec_header.argtypes = [C.c_void_p, C.c_size_t, C.POINTER(C.c_int),
@@ -153,8 +156,9 @@ def codec_bound(log2c: int) -> int:
     return int(lib().orc_codec_bound(log2c))
 
 
-def codec_encode(values: np.ndarray, log2c: int, eb: float) -> bytes:
-    """Encode one chunk (complex128 or complex64 array of 2^log2c values)."""
+def codec_encode(values: np.ndarray, log2c: int, eb: float, mode: int = 0) -> bytes:
+    """Encode one chunk (complex128 or complex64 array of 2^log2c values);
+    mode 0: Lorenzo-1 for every block, mode 1: per-block predictor choice."""
     v = np.ascontiguousarray(values)
     if v.dtype == np.complex128:
         dt = 0
@@ -166,8 +170,8 @@ def codec_encode(values: np.ndarray, log2c: int, eb: float) -> bytes:
     cap = codec_bound(log2c)
     out = np.zeros(cap, dtype=np.uint8)
     nbytes = C.c_size_t(0)
-    st = lib().orc_codec_encode(dt, log2c, float(eb), v.ctypes.data, out.ctypes.data,
-                                cap, C.byref(nbytes))
+    st = lib().orc_codec_encode_mode(dt, log2c, float(eb), int(mode), v.ctypes.data, out.ctypes.data,
+                                     cap, C.byref(nbytes))
     if st != 0:
         raise ValueError("oracle codec encode failed: %d" % st)
     return out[: nbytes.value].tobytes()
@@ -182,7 +186,7 @@ def codec_header(blob: bytes):
     if st != 0:
         raise ValueError("corrupt chunk header")
     return {"dtype": dt.value, "log2c": lc.value, "kind": kind.value,
-            "eb": eb.value, "total_bytes": tot.value}
+            "eb": eb.value, "total_bytes": tot.value, "mode": int.from_bytes(blob[28:32], "little")}
 
 
 def codec_decode(blob: bytes) -> np.ndarray:
