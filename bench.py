@@ -348,6 +348,21 @@ def main():
             sweep["k%d_%s" % (k, mma)] = {"updates_per_s": G * float(1 << n) / dtk, "f_norm": fk[1],
                                           "mfma_ops": stk["mfma_ops"], "fused_ops": stk["fused_ops"]}
         out["mfma_sweep"] = sweep
+        # codec predictor mode 1 (per-block choice), same workload: the same
+        # decoded state, fewer bytes, more encode work
+        sp = Simulator(n, dtype="c64", eb=a.eb, chunk_qubits=min(20, n), k_max=a.k, mma=a.mma,
+                       options={"predictor": 1})
+        run(sp)
+        t1 = time.perf_counter()
+        run(sp)
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - t1
+        stp = sp.stats()
+        fp = sp.fidelity(amps_ref)
+        sp.close()
+        out["predictor_mode1"] = {"updates_per_s": G * float(1 << n) / dtp, "ratio": stp["ratio"],
+                                  "compressed_bytes": stp["compressed_bytes"], "f_norm": fp[1],
+                                  "ratio_mode0": st["ratio"]}
         del amps_ref
         plain_gbs = pst["pass_bytes"] / pst["t_pass"] / 1e9 if pst["t_pass"] else None
         out["comparators"] = {

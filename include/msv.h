@@ -208,7 +208,12 @@ int msv_set_fusion(msv_sim *sim, int k_max, int mma_precision);
  *                  0 = plan every call
  *   "autotune"     1 = choose fusion width and tile size per msv_apply from
  *                  the fixed cost model (the same plan in every process);
- *                  2 = from the model measured once in this process; 0 = off */
+ *                  2 = from the model measured once in this process; 0 = off
+ *   "predictor"    codec predictor mode of every encode from the next one on
+ *                  (0 default: Lorenzo-1; 1: per block the predictor of
+ *                  smallest width, see msv_codec_encode). Codes, and so the
+ *                  decoded state, do not depend on it; exported chunks carry
+ *                  mode 1 once any encode used it since the last init */
 int msv_set_option(msv_sim *sim, const char *key, double value);
 /* Device memory provider (e.g. a framework's caching allocator). alloc returns
  * NULL on failure; both are called on the calling thread. Without it the
@@ -306,16 +311,27 @@ int msv_qasm_parse(const char *text, int *n_qubits, msv_gate *gates, size_t gate
                    double *mats, size_t mat_cap, size_t *n_mat);
 
 /* ---- codec on its own ---------------------------------------------------------
- * Format "MSVC" v1 for a chunk of C = 2^log2_chunk complex values:
+ * Format "MSVC" v1 for a chunk of C = 2^log2_chunk complex values (the paper
+ * compresses every chunk on its own, Sec. 2 offline stage, and leaves the
+ * compressor open, end of the online stage; this format is the library's):
  *   32-byte header: u32 magic 0x4356534D, u8 version 1, u8 kind (0 ZERO,
  *   1 GENERAL), u8 log2C, u8 dtype, f64 eb, u64 total_bytes, u32 n_blocks
- *   (= 2C/64), u32 0. GENERAL chunks continue with u8 W[n_blocks] and
- *   i32 A[n_blocks] (each zero-padded to 8 bytes) and the payload: for stream
- *   block b = 2j + p (j = 64-amplitude block, p = 0 real / 1 imaginary) W[b]
- *   64-bit words whose bit i is bit k of zigzag(q_i - q_(i-1)) (d_0 = 0),
- *   A[b] = q_0. Runs on the GPU. */
+ *   (= 2C/64), u32 predictor mode (0 or 1). GENERAL chunks continue with
+ *   u8 W[n_blocks] and i32 A[n_blocks] (each zero-padded to 8 bytes) and the
+ *   payload: for stream block b = 2j + p (j = 64-amplitude block, p = 0 real /
+ *   1 imaginary) with width w = W[b] & 63 and predictor r = W[b] >> 6, w
+ *   64-bit words whose bit i is bit k of zigzag(d_i), A[b] = q_0, d_0 = 0 and
+ *   (32-bit wrap-around) r = 0 Lorenzo-1: d_i = q_i - q_(i-1); r = 1 none:
+ *   d_i = q_i; r = 2 Lorenzo-2: d_1 = q_1 - q_0, d_i = q_i - 2 q_(i-1) +
+ *   q_(i-2). Mode 0 uses r = 0 for every block; mode 1 takes, per block, the
+ *   predictor of smallest width (ties to the lower r). Runs on the GPU.
+ * msv_codec_encode writes mode 0. */
 int msv_codec_encode(int dtype, int log2_chunk, double eb, const void *host_in,
                      void *host_out, size_t cap, size_t *out_bytes);
+/* msv_codec_encode in predictor mode pred_mode (0 or 1; else MSV_E_ARG). The
+ * decoded values do not depend on the mode. */
+int msv_codec_encode_mode(int dtype, int log2_chunk, double eb, int pred_mode, const void *host_in,
+                          void *host_out, size_t cap, size_t *out_bytes);
 /* Decode one chunk into host_out (2^log2C complex of the header's dtype).
  * MSV_E_CORRUPT on a malformed chunk. */
 int msv_codec_decode(int dtype, const void *host_in, size_t in_bytes, void *host_out);

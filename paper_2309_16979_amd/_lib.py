@@ -60,7 +60,7 @@ EXPORTS = (
     "msv_set_store", "msv_set_fusion", "msv_set_option", "msv_set_device_allocator",
     "msv_set_stream", "msv_init_basis", "msv_init_state", "msv_apply", "msv_prob_one",
     "msv_expect_z", "msv_get_amplitudes", "msv_fidelity", "msv_get_stats", "msv_export_chunk",
-    "msv_codec_encode", "msv_codec_decode", "msv_codec_bound", "msv_adjoint", "msv_batch_run",
+    "msv_codec_encode", "msv_codec_encode_mode", "msv_codec_decode", "msv_codec_bound", "msv_adjoint", "msv_batch_run",
     "msv_batch_adjoint", "msv_plan_export", "msv_get_pass_stats", "msv_codec_encode_static",
     "msv_set_error_bound_mode", "msv_qasm_parse", "msv_autotune_calibrate",
     # include/msv_probe.h
@@ -128,6 +128,8 @@ def load():
                                 C.POINTER(C.c_double), C.POINTER(C.c_size_t)], C.c_int),
         "msv_export_chunk": ([P, C.c_uint64, P, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
         "msv_codec_encode": ([C.c_int, C.c_int, C.c_double, P, P, C.c_size_t, C.POINTER(C.c_size_t)], C.c_int),
+        "msv_codec_encode_mode": ([C.c_int, C.c_int, C.c_double, C.c_int, P, P, C.c_size_t,
+                                   C.POINTER(C.c_size_t)], C.c_int),
         "msv_codec_decode": ([C.c_int, P, C.c_size_t, P], C.c_int),
         "msv_codec_encode_static": ([C.c_int, C.c_int, C.c_double, P, P, C.c_size_t, C.POINTER(C.c_size_t)],
                                     C.c_int),

@@ -55,7 +55,8 @@ int save_ckpt(msv_sim *s, Ckpt &c, Scratch &w)
     HIPCHK(s, hipMemcpyAsync(&total, (const uint64_t *)c.offsets.p + nc, 8, hipMemcpyDeviceToHost, cs));
     HIPCHK(s, hipStreamSynchronize(cs));
     if ((st = dev_alloc(s, c.blob, std::max<uint64_t>(total, 256)))) return st;
-    HIPCHK(s, launch_assemble_chunks(s->is_double() ? 0 : 1, s->log2c, s->eb, (const uint8_t *)d.W.p,
+    HIPCHK(s, launch_assemble_chunks(s->is_double() ? 0 : 1, s->log2c, s->eb, s->export_pred_mode(),
+                                     (const uint8_t *)d.W.p,
                                      (const int32_t *)d.A.p, (const uint32_t *)d.OFF.p, (const uint64_t *)d.heap.p,
                                      (const uint32_t *)w.dst_off.p, (const uint64_t *)c.sizes.p,
                                      (const uint32_t *)w.kinds.p, (const uint64_t *)c.offsets.p, nc,
@@ -101,6 +102,8 @@ int restore_ckpt(msv_sim *s, Ckpt &c, Scratch &w, int tb)
     b.scale = 1.0;
     b.flags = (uint32_t *)w.flags.p;
     b.check_err = 0;
+    b.pred_mode = s->pred_mode;
+    b.in_pred = s->in_pred();
     b.ops = (const OpDesc *)s->ws.ops.p;
     b.pool = s->ws.pool.p;
     HIPCHK(s, launch_pass(s->is_double(), true, true, copy_geom(s, tb), b, cs));
@@ -141,6 +144,8 @@ int init_lambda(msv_sim *s, const uint64_t *masks, const double *coeffs, size_t 
     b.scale = 1.0;
     b.flags = (uint32_t *)w.flags.p;
     b.check_err = 0;
+    b.pred_mode = s->pred_mode;
+    b.in_pred = s->in_pred();
     b.ops = (const OpDesc *)s->ws.ops.p;
     b.pool = s->ws.pool.p;
     b.obs_masks = (const uint64_t *)s->ws.masks.p;
@@ -202,6 +207,8 @@ int run_adjoint_passes(msv_sim *s, const std::vector<Pass> &passes, const PlanOp
             b.part = (double *)(which ? w.lam_part.p : w.psi_part.p);
             b.flags = (uint32_t *)w.flags.p;
             b.check_err = s->check_bound;
+            b.pred_mode = s->pred_mode;
+            b.in_pred = s->in_pred();
             b.ops = (const OpDesc *)s->ws.ops.p;
             b.pool = s->ws.pool.p;
         }
@@ -379,7 +386,7 @@ extern "C" int msv_adjoint(msv_sim *s, const msv_gate *gates, size_t n_gates, co
         a.partials = (double *)s->ws.red.p;
         a.scale = 1.0;
         int groups = 0;
-        HIPCHK(s, launch_reduce(s->is_double(), s->compressed(), s->amps.p, s->st[s->cur].view(),
+        HIPCHK(s, launch_reduce(s->is_double(), s->decode_comp(), s->amps.p, s->st[s->cur].view(),
                                 s->compressed() ? s->step() : 0.0, a, &groups, cs));
         HIPCHK(s, launch_reduce_final(a.partials, groups, (double *)s->ws.red_out.p, cs));
         double o4[4];

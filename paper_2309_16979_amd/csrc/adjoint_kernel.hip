@@ -81,11 +81,13 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(PassGeom geo, Adjoint
     const uint64_t slot = (tile - buf.psi.slot_tile0) * (uint64_t)(32 * NSB);
     double n1 = 0.0, e1 = 0.0, n2 = 0.0, e2 = 0.0;
     const uint32_t w1 = tile_store<T, TB, COMP>(pre, pim, sG, sW, sA, sOff, buf.psi.amps_out, buf.psi.out, slot,
-                                                buf.psi.inv_step, buf.psi.step, buf.psi.check_err, buf.psi.flags, n1,
+                                                buf.psi.inv_step, buf.psi.step, buf.psi.check_err, buf.psi.pred_mode,
+                                                buf.psi.flags, n1,
                                                 e1, wave, lane);
     __syncthreads();
     const uint32_t w2 = tile_store<T, TB, COMP>(lre, lim, sG, sW, sA, sOff, buf.lam.amps_out, buf.lam.out, slot,
-                                                buf.lam.inv_step, buf.lam.step, buf.lam.check_err, buf.lam.flags, n2,
+                                                buf.lam.inv_step, buf.lam.step, buf.lam.check_err, buf.lam.pred_mode,
+                                                buf.lam.flags, n2,
                                                 e2, wave, lane);
     n1 = wave_sum_f64(n1);
     e1 = wave_max_f64(e1);

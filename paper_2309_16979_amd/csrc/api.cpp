@@ -231,9 +231,12 @@ int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOpt
         b.part = part + 3 * offs[p];
         b.flags = (uint32_t *)s->ws.flags.p;
         b.check_err = s->check_bound;
+        b.pred_mode = s->pred_mode;
+        b.in_pred = s->in_pred();
         b.ops = (const OpDesc *)s->ws.ops.p;
         b.pool = s->ws.pool.p;
         const bool c = s->compressed();
+        if (c && s->pred_mode) s->pred_used = true;
         if (s->time_passes) HIPCHK(s, hipEventRecord(ev[2 * p], stream));
         HIPCHK(s, launch_pass(s->is_double(), c, c, geoms[p], b, stream));
         if (s->time_passes) HIPCHK(s, hipEventRecord(ev[2 * p + 1], stream));
@@ -488,6 +491,9 @@ int msv_set_option(msv_sim *s, const char *key, double v)
         s->cpu_threads = iv;
     } else if (!strcmp(key, "time_passes")) {
         s->time_passes = v != 0.0;
+    } else if (!strcmp(key, "predictor")) {
+        if (v != iv || iv < 0 || iv > 1) return fail(s, MSV_E_ARG, "predictor in {0, 1}");
+        s->pred_mode = iv;
     } else if (!strcmp(key, "batch_chunks")) {
         if (v != iv || iv < 0) return fail(s, MSV_E_ARG, "batch_chunks >= 0");
         s->batch_chunks = iv;
@@ -561,6 +567,9 @@ int msv_init_basis(msv_sim *s, uint64_t index)
         HIPCHK(s, hipStreamSynchronize(stream));
         s->compressed_words = 0;
     }
+    // device-store basis blocks use predictor 0; the host store encodes its
+    // one nonzero chunk with the current mode
+    s->pred_used = s->store == MSV_STORE_HOST_PINNED && s->pred_mode != 0;
     s->inited = true;
     return MSV_OK;
 }
@@ -574,6 +583,7 @@ int msv_init_state(msv_sim *s, const void *host)
     reset_stats(s);
     hipStream_t stream = s->stream();
     const size_t bytes = s->elt() << s->n;
+    s->pred_used = s->pred_mode != 0;
     if (s->store == MSV_STORE_HOST_PINNED) {
         if ((st = init_host_store_state(s, host))) return st;
         s->inited = true;
@@ -616,6 +626,7 @@ int msv_init_state(msv_sim *s, const void *host)
     b.part = (double *)s->ws.part.p;
     b.flags = (uint32_t *)s->ws.flags.p;
     b.check_err = s->check_bound;
+    b.pred_mode = s->pred_mode;
     b.ops = (const OpDesc *)s->ws.ops.p;
     b.pool = s->ws.pool.p;
     hipError_t e = launch_pass(s->is_double(), false, true, geoms[0], b, stream);
@@ -753,7 +764,7 @@ static int reduce_state(msv_sim *s, ReduceArgs a, double *out4)
     if (s->store == MSV_STORE_HOST_PINNED) {
         if ((st = host_store_reduce(s, a, &groups))) return st;
     } else {
-        HIPCHK(s, launch_reduce(s->is_double(), s->compressed(), s->amps.p, s->st[s->cur].view(),
+        HIPCHK(s, launch_reduce(s->is_double(), s->decode_comp(), s->amps.p, s->st[s->cur].view(),
                                 s->compressed() ? s->step() : 0.0, a, &groups, stream));
     }
     HIPCHK(s, launch_reduce_final(a.partials, groups, (double *)s->ws.red_out.p, stream));
@@ -826,7 +837,7 @@ int msv_get_amplitudes(msv_sim *s, uint64_t first, uint64_t count, void *host_ou
             if ((st = host_store_decode_range(s, b, cnt, s->ws.tmp2.p))) return st;
         } else {
             // compressed blocks, or plain amplitudes with a pending renormalisation factor
-            HIPCHK(s, launch_decode_range(s->is_double(), s->compressed(), s->amps.p, s->st[s->cur].view(),
+            HIPCHK(s, launch_decode_range(s->is_double(), s->decode_comp(), s->amps.p, s->st[s->cur].view(),
                                           s->compressed() ? s->step() : 0.0, s->scale, b, cnt, s->ws.tmp2.p,
                                           stream));
         }
@@ -866,7 +877,7 @@ int msv_fidelity(msv_sim *s, const double *ref, double *f_raw, double *f_norm)
         if (s->store == MSV_STORE_HOST_PINNED) {
             if ((st = host_store_reduce(s, a, &groups))) return st;
         } else {
-            HIPCHK(s, launch_reduce(s->is_double(), s->compressed(), s->amps.p, s->st[s->cur].view(),
+            HIPCHK(s, launch_reduce(s->is_double(), s->decode_comp(), s->amps.p, s->st[s->cur].view(),
                                     s->compressed() ? s->step() : 0.0, a, &groups, stream));
         }
         total_groups += groups;

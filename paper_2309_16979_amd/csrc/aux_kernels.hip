@@ -56,9 +56,9 @@ constexpr int kRedGroups = 2048;
 // decoded both planes at a time in rounds of up to 16 per wave: lane 2a + p
 // fetches the metadata of round block a, plane p, then every block's payload
 // word `lane` is loaded before one wait. f(G, xr, xi) runs per decoded block.
-template <typename T, bool COMP, typename F>
+template <typename T, bool COMP, bool PRED, typename F>
 // stage: 128 words of LDS for this wave, through which the decode broadcasts
-// plane words (unpack_codes4_lds).
+// plane words (unpack_codes4_lds). PRED = false: every block uses predictor 0.
 static __device__ __forceinline__ void for_amp_blocks(const void *amps, const BlockStore &st, double step,
                                                       uint64_t first, uint64_t nab, int wave, int lane,
                                                       uint64_t *stage, F &&f)
@@ -96,7 +96,8 @@ static __device__ __forceinline__ void for_amp_blocks(const void *amps, const Bl
         uint64_t mine[2 * RA];
 #pragma unroll
         for (int j = 0; j < 2 * RA; ++j) {
-            const uint32_t W = (uint32_t)__builtin_amdgcn_readlane((int)wv, j);
+            const uint32_t wj = (uint32_t)__builtin_amdgcn_readlane((int)wv, j);
+            const uint32_t W = PRED ? wbyte_width(wj) : wj;   // without PRED the byte is the width
             const uint32_t off = (uint32_t)__builtin_amdgcn_readlane((int)ov, j);
             mine[j] = 0;
             if ((uint32_t)lane < W) mine[j] = st.heap[(uint64_t)off + lane];
@@ -118,7 +119,7 @@ static __device__ __forceinline__ void for_amp_blocks(const void *amps, const Bl
 #pragma unroll
                 for (int p = 0; p < 4; ++p) stage[32 * p + lane] = mine[2 * a + p];
             }
-            unpack_codes4_lds(stage, W4, A4, q4);
+            unpack_codes4_lds<PRED>(stage, W4, A4, q4);
             f(first + k, (double)dequantize<T>(q4[0], step), (double)dequantize<T>(q4[1], step));
             if (k + stride < nab)
                 f(first + k + stride, (double)dequantize<T>(q4[2], step), (double)dequantize<T>(q4[3], step));
@@ -126,7 +127,7 @@ static __device__ __forceinline__ void for_amp_blocks(const void *amps, const Bl
     }
 }
 
-template <typename T, bool COMP>
+template <typename T, int COMP>
 __global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, BlockStore st, double step,
                                                           ReduceArgs a)
 {
@@ -159,7 +160,7 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, Bloc
     const double s0 = (lane & 1) ? -1.0 : 1.0, s1 = (lane & 2) ? -1.0 : 1.0, s2 = (lane & 4) ? -1.0 : 1.0,
                  s3 = (lane & 8) ? -1.0 : 1.0, s4 = (lane & 16) ? -1.0 : 1.0, s5 = (lane & 32) ? -1.0 : 1.0;
     __shared__ uint64_t stage[NW * 128];
-    for_amp_blocks<T, COMP>(amps, st, step, first, nab, wave, lane, stage + 128 * wave,
+    for_amp_blocks<T, COMP != 0, COMP == 2>(amps, st, step, first, nab, wave, lane, stage + 128 * wave,
                             [&](uint64_t G, double xr, double xi) {
         xr *= a.scale;
         xi *= a.scale;
@@ -207,7 +208,16 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, Bloc
     }
 }
 
-hipError_t launch_reduce(bool is_double, bool compressed, const void *amps, BlockStore st,
+template <typename T>
+static void reduce_comp(int comp, dim3 grid, dim3 block, hipStream_t stream, const void *amps, const BlockStore &st,
+                        double step, const ReduceArgs &a)
+{
+    if (comp == 2) hipLaunchKernelGGL((reduce_kernel<T, 2>), grid, block, 0, stream, amps, st, step, a);
+    else if (comp == 1) hipLaunchKernelGGL((reduce_kernel<T, 1>), grid, block, 0, stream, amps, st, step, a);
+    else hipLaunchKernelGGL((reduce_kernel<T, 0>), grid, block, 0, stream, amps, st, step, a);
+}
+
+hipError_t launch_reduce(bool is_double, int comp, const void *amps, BlockStore st,
                          double step, const ReduceArgs &a, int *n_groups, hipStream_t stream)
 {
     const uint64_t nab = a.amp_count >> 6;
@@ -216,13 +226,8 @@ hipError_t launch_reduce(bool is_double, bool compressed, const void *amps, Bloc
     if (g == 0) g = 1;
     *n_groups = (int)g;
     const dim3 grid((unsigned)g), block(kThreads);
-    if (is_double) {
-        if (compressed) hipLaunchKernelGGL((reduce_kernel<double, true>), grid, block, 0, stream, amps, st, step, a);
-        else hipLaunchKernelGGL((reduce_kernel<double, false>), grid, block, 0, stream, amps, st, step, a);
-    } else {
-        if (compressed) hipLaunchKernelGGL((reduce_kernel<float, true>), grid, block, 0, stream, amps, st, step, a);
-        else hipLaunchKernelGGL((reduce_kernel<float, false>), grid, block, 0, stream, amps, st, step, a);
-    }
+    if (is_double) reduce_comp<double>(comp, grid, block, stream, amps, st, step, a);
+    else reduce_comp<float>(comp, grid, block, stream, amps, st, step, a);
     return hipGetLastError();
 }
 
@@ -291,7 +296,7 @@ hipError_t launch_pass_stats(const double *part, const uint64_t *pass_offsets, i
 
 // ------------------------------------------------------------ range decode
 
-template <typename T, bool COMP>
+template <typename T, int COMP>
 __global__ __launch_bounds__(kThreads) void decode_range_kernel(const void *amps, BlockStore st, double step,
                                                                 double scale, uint64_t first, uint64_t nab, void *out)
 {
@@ -300,7 +305,7 @@ __global__ __launch_bounds__(kThreads) void decode_range_kernel(const void *amps
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     constexpr int NW = kThreads / 64;
     __shared__ uint64_t stage[NW * 128];
-    for_amp_blocks<T, COMP>(amps, st, step, first, nab, wave, lane, stage + 128 * wave,
+    for_amp_blocks<T, COMP != 0, COMP == 2>(amps, st, step, first, nab, wave, lane, stage + 128 * wave,
                             [&](uint64_t G, double xr, double xi) {
         V2 v;
         v.x = (T)xr;
@@ -310,7 +315,23 @@ __global__ __launch_bounds__(kThreads) void decode_range_kernel(const void *amps
     });
 }
 
-hipError_t launch_decode_range(bool is_double, bool compressed, const void *amps, BlockStore st, double step,
+template <typename T>
+static void decode_range_comp(int comp, dim3 grid, dim3 block, hipStream_t stream, const void *amps,
+                              const BlockStore &st, double step, double scale, uint64_t first, uint64_t nab,
+                              void *out)
+{
+    if (comp == 2)
+        hipLaunchKernelGGL((decode_range_kernel<T, 2>), grid, block, 0, stream, amps, st, step, scale, first, nab,
+                           out);
+    else if (comp == 1)
+        hipLaunchKernelGGL((decode_range_kernel<T, 1>), grid, block, 0, stream, amps, st, step, scale, first, nab,
+                           out);
+    else
+        hipLaunchKernelGGL((decode_range_kernel<T, 0>), grid, block, 0, stream, amps, st, step, scale, first, nab,
+                           out);
+}
+
+hipError_t launch_decode_range(bool is_double, int comp, const void *amps, BlockStore st, double step,
                                double scale, uint64_t amp_begin, uint64_t amp_count, void *out, hipStream_t stream)
 {
     const uint64_t nab = amp_count >> 6;
@@ -318,18 +339,8 @@ hipError_t launch_decode_range(bool is_double, bool compressed, const void *amps
     if (g > 65536) g = 65536;
     if (g == 0) return hipSuccess;
     const dim3 grid((unsigned)g), block(kThreads);
-    if (is_double && compressed)
-        hipLaunchKernelGGL((decode_range_kernel<double, true>), grid, block, 0, stream, amps, st, step, scale,
-                           amp_begin >> 6, nab, out);
-    else if (is_double)
-        hipLaunchKernelGGL((decode_range_kernel<double, false>), grid, block, 0, stream, amps, st, step, scale,
-                           amp_begin >> 6, nab, out);
-    else if (compressed)
-        hipLaunchKernelGGL((decode_range_kernel<float, true>), grid, block, 0, stream, amps, st, step, scale,
-                           amp_begin >> 6, nab, out);
-    else
-        hipLaunchKernelGGL((decode_range_kernel<float, false>), grid, block, 0, stream, amps, st, step, scale,
-                           amp_begin >> 6, nab, out);
+    if (is_double) decode_range_comp<double>(comp, grid, block, stream, amps, st, step, scale, amp_begin >> 6, nab, out);
+    else decode_range_comp<float>(comp, grid, block, stream, amps, st, step, scale, amp_begin >> 6, nab, out);
     return hipGetLastError();
 }
 
@@ -337,8 +348,8 @@ hipError_t launch_decode_range(bool is_double, bool compressed, const void *amps
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void encode_chunks_kernel(const T *vals, uint64_t n_blocks,
-                                                                 double inv_step, double step, uint8_t *W,
-                                                                 int32_t *A, uint64_t *slots,
+                                                                 double inv_step, double step, int pred_mode,
+                                                                 uint8_t *W, int32_t *A, uint64_t *slots,
                                                                  unsigned long long *err_bits, uint32_t *flags)
 {
     constexpr int NW = kThreads / 64;
@@ -352,12 +363,20 @@ __global__ __launch_bounds__(kThreads) void encode_chunks_kernel(const T *vals, 
         const int32_t q = quantize<T>(x, inv_step, bad);
         const T xr = dequantize<T>(q, step);
         err = fmax(err, __builtin_fabs((double)x - (double)xr));
-        const uint32_t u = residual_zigzag(q);
-        const uint32_t w = block_width(u);
+        const int32_t d1 = residual1(q);
+        uint32_t u = zigzag(d1);
+        uint32_t w = block_width(u), pred = 0;
+        if (pred_mode) {
+            uint32_t un, u2;
+            residuals_alt(q, d1, un, u2);
+            const uint32_t wn = block_width(un), w2 = block_width(u2);
+            if (wn < w) { w = wn; pred = 1; u = un; }
+            if (w2 < w) { w = w2; pred = 2; u = u2; }
+        }
         const uint64_t mine = pack_planes(u, w);
         const int32_t a0 = __builtin_amdgcn_readlane(q, 0);
         if (lane < w) slots[b * 32 + lane] = mine;
-        if (lane == 0) { W[b] = (uint8_t)w; A[b] = a0; }
+        if (lane == 0) { W[b] = (uint8_t)(w | (pred << 6)); A[b] = a0; }
     }
     err = wave_max_f64(err);
     if (lane == 0) atomicMax(err_bits, (unsigned long long)__double_as_longlong(err));
@@ -366,7 +385,7 @@ __global__ __launch_bounds__(kThreads) void encode_chunks_kernel(const T *vals, 
 
 hipError_t launch_encode_chunks(bool is_double, const void *vals, uint64_t n_blocks_total, double inv_step,
                                 uint8_t *W, int32_t *A, uint64_t *slot_words, double *err_max_bits,
-                                uint32_t *flags, double step, hipStream_t stream)
+                                uint32_t *flags, double step, int pred_mode, hipStream_t stream)
 {
     uint64_t g = (n_blocks_total + 3) / 4;
     if (g > 65536) g = 65536;
@@ -374,10 +393,12 @@ hipError_t launch_encode_chunks(bool is_double, const void *vals, uint64_t n_blo
     unsigned long long *eb = reinterpret_cast<unsigned long long *>(err_max_bits);
     if (is_double)
         hipLaunchKernelGGL(encode_chunks_kernel<double>, dim3((unsigned)g), dim3(kThreads), 0, stream,
-                           (const double *)vals, n_blocks_total, inv_step, step, W, A, slot_words, eb, flags);
+                           (const double *)vals, n_blocks_total, inv_step, step, pred_mode, W, A, slot_words, eb,
+                           flags);
     else
         hipLaunchKernelGGL(encode_chunks_kernel<float>, dim3((unsigned)g), dim3(kThreads), 0, stream,
-                           (const float *)vals, n_blocks_total, inv_step, step, W, A, slot_words, eb, flags);
+                           (const float *)vals, n_blocks_total, inv_step, step, pred_mode, W, A, slot_words, eb,
+                           flags);
     return hipGetLastError();
 }
 
@@ -408,23 +429,31 @@ static __device__ uint64_t block_sum(uint64_t v, uint64_t *sbuf)
     return block_exclusive_scan(v, &ex, sbuf);
 }
 
-// Four codec widths packed in a word: their sum (v_sad_u8 against zero) and
-// whether any of them exceeds 32 (a byte is > 32 when it is >= 64, or when
-// bit 5 is set together with any of bits 0..4).
+// Four width bytes packed in a word (width in bits 0..5, predictor in bits
+// 6..7): the sum of their widths (v_sad_u8 against zero) and whether any is
+// malformed: a width above 32 (bit 5 set together with any of bits 0..4), or
+// a predictor the chunk's mode does not allow (mode 0: none but 0; mode 1:
+// 0..2).
 static __device__ __forceinline__ uint32_t width4_sum(uint32_t x, uint32_t acc)
 {
-    return __builtin_amdgcn_sad_u8(x, 0u, acc);
+    return __builtin_amdgcn_sad_u8(x & 0x3F3F3F3Fu, 0u, acc);
 }
-static __device__ __forceinline__ uint32_t width4_bad(uint32_t x)
+static __device__ __forceinline__ uint32_t width4_bad(uint32_t x, uint32_t mode)
 {
     const uint32_t low = ((x & 0x1F1F1F1Fu) + 0x1F1F1F1Fu) & 0x20202020u;
-    return (x & 0xC0C0C0C0u) | (x & low);
+    const uint32_t pred_bad = mode ? (x & 0x80808080u & ((x & 0x40404040u) << 1)) : (x & 0xC0C0C0C0u);
+    return pred_bad | (x & low);
+}
+static __device__ __forceinline__ bool width_bad(uint32_t v, uint32_t mode)
+{
+    return (v & 63u) > 32u || (v >> 6) > (mode ? 2u : 0u);
 }
 
-// Sum of the widths w[0..n) over the workgroup's threads (per-thread part
-// returned; the caller reduces), with bit flags of widths above 32 in *bad.
+// Sum of the widths of the width bytes w[0..n) over the workgroup's threads
+// (per-thread part returned; the caller reduces), with bit flags of malformed
+// bytes (for predictor mode `mode`) in *bad.
 // n and the address of w must be multiples of 16 for the wide path.
-static __device__ __forceinline__ uint64_t widths_part(const uint8_t *w, uint64_t n, uint32_t *bad)
+static __device__ __forceinline__ uint64_t widths_part(const uint8_t *w, uint64_t n, uint32_t mode, uint32_t *bad)
 {
     uint64_t s = 0;
     uint32_t b = 0;
@@ -437,13 +466,13 @@ static __device__ __forceinline__ uint64_t widths_part(const uint8_t *w, uint64_
             t = width4_sum(x.z, t);
             t = width4_sum(x.w, t);
             s += t;
-            b |= width4_bad(x.x) | width4_bad(x.y) | width4_bad(x.z) | width4_bad(x.w);
+            b |= width4_bad(x.x, mode) | width4_bad(x.y, mode) | width4_bad(x.z, mode) | width4_bad(x.w, mode);
         }
     } else {
         for (uint64_t i = threadIdx.x; i < n; i += kThreads) {
             const uint32_t v = w[i];
-            s += v;
-            b |= v > 32 ? 1u : 0u;
+            s += v & 63u;
+            b |= width_bad(v, mode) ? 1u : 0u;
         }
     }
     *bad |= b;
@@ -469,7 +498,7 @@ __global__ __launch_bounds__(kThreads) void scan_chunks_kernel(const uint8_t *W,
     const uint8_t *w = W + c * nb;
     const int32_t *a = A + c * nb;
     uint32_t bad = 0;
-    const uint64_t before = block_sum(widths_part(w, s0, &bad), sbuf);
+    const uint64_t before = block_sum(widths_part(w, s0, 1u, &bad), sbuf);
     bad = 0;   // widths outside the segment are checked by their own workgroup
     uint64_t carry = before;
     // tiles of 4 * kThreads blocks, four consecutive blocks per thread
@@ -478,8 +507,9 @@ __global__ __launch_bounds__(kThreads) void scan_chunks_kernel(const uint8_t *W,
         uint32_t v[4], sum = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            v[k] = b + k < s1 ? w[b + k] : 0u;
-            bad |= v[k] > 32 ? 1u : 0u;
+            const uint32_t wb = b + k < s1 ? w[b + k] : 0u;
+            bad |= width_bad(wb, 1u) ? 1u : 0u;
+            v[k] = wb & 63u;
             sum += v[k];
         }
         uint64_t ex;
@@ -496,7 +526,7 @@ __global__ __launch_bounds__(kThreads) void scan_chunks_kernel(const uint8_t *W,
     if (!first) return;   // whole workgroup
     // first segment: the whole chunk's total (widths from s1 on) and kind
     uint32_t ignore = 0;
-    const uint64_t rest = block_sum(widths_part(w + s1, nb - s1, &ignore), sbuf);
+    const uint64_t rest = block_sum(widths_part(w + s1, nb - s1, 1u, &ignore), sbuf);
     const uint64_t total = carry + rest;   // the same in every thread
     bool general = total != 0;
     if (!general) {
@@ -570,7 +600,7 @@ hipError_t launch_scan_sizes(const uint64_t *sizes, uint64_t n, uint64_t *offset
 // blocks' widths and anchors side by side, the lane of a chunk's first block
 // writes that chunk's header, then the wave copies the payload of its blocks
 // one block at a time (lanes = the block's plane words). nb is a power of two.
-__global__ __launch_bounds__(kThreads) void assemble_chunks_kernel(int dtype, int log2c, double eb,
+__global__ __launch_bounds__(kThreads) void assemble_chunks_kernel(int dtype, int log2c, double eb, int pred_mode,
                                                                    const uint8_t *W, const int32_t *A,
                                                                    const uint32_t *src_off, const uint64_t *src,
                                                                    const uint32_t *dst_off, const uint64_t *sizes,
@@ -600,7 +630,7 @@ __global__ __launch_bounds__(kThreads) void assemble_chunks_kernel(int dtype, in
             h[4] = (uint32_t)(sizes[c] & 0xffffffffull);
             h[5] = (uint32_t)(sizes[c] >> 32);
             h[6] = (uint32_t)nb;
-            h[7] = 0u;
+            h[7] = (uint32_t)pred_mode;
             if (general) {
                 // zero padding after W and after A
                 for (uint64_t i = 32 + nb; i < a_off; ++i) o[i] = 0;
@@ -610,8 +640,9 @@ __global__ __launch_bounds__(kThreads) void assemble_chunks_kernel(int dtype, in
         uint32_t w = 0;
         uint64_t d = 0, so = 0;
         if (general) {
-            w = W[gb];
-            o[32 + b] = (uint8_t)w;
+            const uint32_t wb = W[gb];
+            o[32 + b] = (uint8_t)wb;
+            w = wb & 63u;
             reinterpret_cast<int32_t *>(o + a_off)[b] = A[gb];
             d = (uint64_t)(uintptr_t)(reinterpret_cast<uint64_t *>(o) + p_off / 8 + dst_off[gb]);
             so = src_off ? (uint64_t)src_off[gb] : gb * 32;
@@ -630,7 +661,7 @@ __global__ __launch_bounds__(kThreads) void assemble_chunks_kernel(int dtype, in
     }
 }
 
-hipError_t launch_assemble_chunks(int dtype, int log2c, double eb, const uint8_t *W, const int32_t *A,
+hipError_t launch_assemble_chunks(int dtype, int log2c, double eb, int pred_mode, const uint8_t *W, const int32_t *A,
                                   const uint32_t *src_off, const uint64_t *src_heap, const uint32_t *dst_off,
                                   const uint64_t *sizes, const uint32_t *kinds, const uint64_t *offsets,
                                   uint64_t n_chunks, uint8_t *out, hipStream_t stream)
@@ -640,8 +671,8 @@ hipError_t launch_assemble_chunks(int dtype, int log2c, double eb, const uint8_t
     uint64_t g = (nb * n_chunks + kThreads - 1) / kThreads;
     if (g > 4096) g = 4096;
     if (g == 0) return hipSuccess;
-    hipLaunchKernelGGL(assemble_chunks_kernel, dim3((unsigned)g), dim3(kThreads), 0, stream, dtype, log2c, eb, W, A,
-                       src_off, src_heap, dst_off, sizes, kinds, offsets, nb, n_chunks, out);
+    hipLaunchKernelGGL(assemble_chunks_kernel, dim3((unsigned)g), dim3(kThreads), 0, stream, dtype, log2c, eb,
+                       pred_mode, W, A, src_off, src_heap, dst_off, sizes, kinds, offsets, nb, n_chunks, out);
     return hipGetLastError();
 }
 
@@ -668,15 +699,16 @@ __global__ __launch_bounds__(kThreads) void parse_chunks_kernel(const uint8_t *b
     // header first: nothing past it is read unless the header is consistent
     // with the bytes actually staged for this chunk
     bool hdr_bad = have < 32;
-    uint32_t kind = 0;
+    uint32_t kind = 0, mode = 0;
     uint64_t total = 0;
     if (!hdr_bad) {
         const uint32_t *h = reinterpret_cast<const uint32_t *>(o);
         const uint32_t meta = h[1];
         kind = (meta >> 8) & 0xffu;
+        mode = h[7];
         total = (uint64_t)h[4] | ((uint64_t)h[5] << 32);
         hdr_bad = h[0] != 0x4356534Du || (meta & 0xffu) != 1u || kind > 1u ||
-                  ((meta >> 16) & 0xffu) != (uint32_t)log2c || h[6] != (uint32_t)nb || h[7] != 0u ||
+                  ((meta >> 16) & 0xffu) != (uint32_t)log2c || h[6] != (uint32_t)nb || mode > 1u ||
                   total != have || (kind == 0 && total != 32) || (kind == 1 && total < p_off);
     }
     const bool general = !hdr_bad && kind == 1;
@@ -686,8 +718,8 @@ __global__ __launch_bounds__(kThreads) void parse_chunks_kernel(const uint8_t *b
     uint32_t wbad = 0;
     uint64_t pre = 0, all = 0;
     if (general) {
-        pre = widths_part(wb, s0, &wbad);
-        all = pre + widths_part(wb + s0, nb - s0, &wbad);
+        pre = widths_part(wb, s0, mode, &wbad);
+        all = pre + widths_part(wb + s0, nb - s0, mode, &wbad);
     }
     if (wbad) sbad = 1;
     const uint64_t words = block_sum(all, sbuf);
@@ -703,7 +735,7 @@ __global__ __launch_bounds__(kThreads) void parse_chunks_kernel(const uint8_t *b
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             w[k] = ok && b + k < s1 ? wb[b + k] : 0u;
-            sum += w[k];
+            sum += w[k] & 63u;
         }
         uint64_t ex;
         const uint64_t tsum = block_exclusive_scan(sum, &ex, sbuf);
@@ -716,7 +748,7 @@ __global__ __launch_bounds__(kThreads) void parse_chunks_kernel(const uint8_t *b
                 A[gb] = ok ? reinterpret_cast<const int32_t *>(o + a_off)[b + k] : 0;
                 OFF[gb] = ok ? (uint32_t)run : 0u;
             }
-            run += w[k];
+            run += w[k] & 63u;
         }
         carry += tsum;
     }

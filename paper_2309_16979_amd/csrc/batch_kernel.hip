@@ -52,7 +52,7 @@ __global__ __launch_bounds__(kThreads, (PassOccupancy<TB, KMAX>::waves)) void ba
         __syncthreads();
         if (!s_go) break;
         const uint64_t local = item - prefix[lo];
-        pass_tile<T, TB, true, true, KMAX, MMA_NONE>(d.geo, d.buf, d.geo.tile_begin + local, local);
+        pass_tile<T, TB, true, true, KMAX, MMA_NONE, false>(d.geo, d.buf, d.geo.tile_begin + local, local);
         // release: every wave makes its own stores of the tile visible to the
         // whole device (consumers may run on another XCD, behind another L2)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");

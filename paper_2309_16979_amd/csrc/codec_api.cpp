@@ -49,11 +49,11 @@ uint64_t pad8(uint64_t x) { return (x + 7) & ~7ull; }
 
 extern "C" {
 
-int msv_codec_encode(int dtype, int log2c, double eb, const void *host_in, void *host_out, size_t cap,
-                     size_t *out_bytes)
+int msv_codec_encode_mode(int dtype, int log2c, double eb, int pred_mode, const void *host_in, void *host_out,
+                          size_t cap, size_t *out_bytes)
 {
     if ((dtype != MSV_C128 && dtype != MSV_C64) || log2c < 6 || log2c > 30 || !host_in || !out_bytes ||
-        !(eb > 0.0) || !std::isfinite(eb))
+        !(eb > 0.0) || !std::isfinite(eb) || (pred_mode != 0 && pred_mode != 1))
         return cfail(MSV_E_ARG, "msv_codec_encode: bad argument");
     const bool dbl = dtype == MSV_C128;
     const uint64_t C = 1ull << log2c, nb = 2 * C / 64;
@@ -76,11 +76,12 @@ int msv_codec_encode(int dtype, int log2c, double eb, const void *host_in, void 
     CHK(hipMemsetAsync(meta, 0, 64, s));
     CHK(hipMemsetAsync(kinds_flags, 0, 16, s));
     const double inv_step = 1.0 / (2.0 * eb), step = 2.0 * eb;
-    CHK(launch_encode_chunks(dbl, vals, nb, inv_step, W, A, slots, (double *)(meta + 3), kinds_flags + 1, step, s));
+    CHK(launch_encode_chunks(dbl, vals, nb, inv_step, W, A, slots, (double *)(meta + 3), kinds_flags + 1, step,
+                             pred_mode, s));
     CHK(launch_scan_chunks(W, A, nb, 1, off, meta, kinds_flags, kinds_flags + 1, s));
     CHK(launch_scan_sizes(meta, 1, meta + 1, s));
-    CHK(launch_assemble_chunks(dtype == MSV_C128 ? 0 : 1, log2c, eb, W, A, nullptr, slots, off, meta, kinds_flags,
-                               meta + 1, 1, out, s));
+    CHK(launch_assemble_chunks(dtype == MSV_C128 ? 0 : 1, log2c, eb, pred_mode, W, A, nullptr, slots, off, meta,
+                               kinds_flags, meta + 1, 1, out, s));
     uint64_t hmeta[4];
     uint32_t hkf[2];
     CHK(hipMemcpyAsync(hmeta, meta, 32, hipMemcpyDeviceToHost, s));
@@ -91,6 +92,12 @@ int msv_codec_encode(int dtype, int log2c, double eb, const void *host_in, void 
     if (!host_out || cap < hmeta[0]) return cfail(MSV_E_ARG, "output buffer too small");
     CHK(hipMemcpy(host_out, out, hmeta[0], hipMemcpyDeviceToHost));
     return MSV_OK;
+}
+
+int msv_codec_encode(int dtype, int log2c, double eb, const void *host_in, void *host_out, size_t cap,
+                     size_t *out_bytes)
+{
+    return msv_codec_encode_mode(dtype, log2c, eb, 0, host_in, host_out, cap, out_bytes);
 }
 
 int msv_codec_decode(int dtype, const void *host_in, size_t in_bytes, void *host_out)
@@ -126,7 +133,7 @@ int msv_codec_decode(int dtype, const void *host_in, size_t in_bytes, void *host
     CHK(hipMemsetAsync(flags, 0, 8, s));
     CHK(launch_parse_chunks(blob, meta, meta + 1, 1, log2c, W, A, OFF, flags, s));
     BlockStore bs{W, A, OFF, (uint64_t *)blob, nullptr, 0};
-    CHK(launch_decode_range(dbl, true, nullptr, bs, 2.0 * eb, 1.0, 0, C, out, s));
+    CHK(launch_decode_range(dbl, 2, nullptr, bs, 2.0 * eb, 1.0, 0, C, out, s));
     uint32_t hf = 0;
     CHK(hipMemcpyAsync(&hf, flags, 4, hipMemcpyDeviceToHost, s));
     CHK(hipStreamSynchronize(s));
@@ -162,7 +169,8 @@ int msv_export_chunk(msv_sim *s, uint64_t chunk, void *host_out, size_t cap, siz
     CHK(hipMemsetAsync(kf, 0, 16, st));
     CHK(launch_scan_chunks((const uint8_t *)d.W.p + b0, (const int32_t *)d.A.p + b0, nb, 1, off, meta, kf, kf + 1, st));
     CHK(launch_scan_sizes(meta, 1, meta + 1, st));
-    CHK(launch_assemble_chunks(s->is_double() ? 0 : 1, s->log2c, s->eb, (const uint8_t *)d.W.p + b0,
+    CHK(launch_assemble_chunks(s->is_double() ? 0 : 1, s->log2c, s->eb, s->export_pred_mode(),
+                               (const uint8_t *)d.W.p + b0,
                                (const int32_t *)d.A.p + b0, (const uint32_t *)d.OFF.p + b0,
                                (const uint64_t *)d.heap.p, off, meta, kf, meta + 1, 1, out, st));
     uint64_t size = 0;

@@ -4,6 +4,13 @@
 // i. Prediction residuals use a DPP wave shift, the decode prefix sum a DPP
 // Hillis-Steele scan within rows of 16 plus two row broadcasts, the width an
 // OR reduction, and bit-plane packing one ballot per plane.
+//
+// A block's width byte holds its width (bits 0..5, 0..32) and its predictor
+// (bits 6..7): 0 Lorenzo-1 (d_i = q_i - q_(i-1)), 1 none (d_i = q_i),
+// 2 Lorenzo-2 (d_1 = q_1 - q_0, d_i = q_i - 2 q_(i-1) + q_(i-2)); d_0 = 0 and
+// the anchor is q_0 for all three; arithmetic wraps modulo 2^32. Predictor
+// mode 0 uses Lorenzo-1 only; mode 1 keeps, per block, the predictor with the
+// smallest width (ties to the lower id).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -66,16 +73,34 @@ __device__ __forceinline__ T dequantize(int32_t q, double step)
     return (T)((double)q * step);
 }
 
-// Zigzag of the Lorenzo-1 residual d_i = q_i - q_(i-1), d_0 = 0. The shifted
-// copy stays a separate v_mov_dpp (the empty asm hides it from the DPP
-// combiner), so the subtraction is an ordinary VALU op whose operand order is
-// explicit.
-__device__ __forceinline__ uint32_t residual_zigzag(int32_t q)
+__device__ __forceinline__ uint32_t zigzag(int32_t d) { return ((uint32_t)d << 1) ^ (uint32_t)(d >> 31); }
+
+// Width and predictor fields of a width byte.
+__device__ __forceinline__ uint32_t wbyte_width(uint32_t wb) { return wb & 63u; }
+__device__ __forceinline__ uint32_t wbyte_pred(uint32_t wb) { return wb >> 6; }
+
+// Lorenzo-1 residual d_i = q_i - q_(i-1), d_0 = 0. The shifted copy stays a
+// separate v_mov_dpp (the empty asm hides it from the DPP combiner), so the
+// subtraction is an ordinary VALU op whose operand order is explicit.
+__device__ __forceinline__ int32_t residual1(int32_t q)
 {
     uint32_t prev = wave_shift_up1((uint32_t)q);
     asm("" : "+v"(prev));
-    const int32_t d = lane_id() == 0 ? 0 : (int32_t)((uint32_t)q - prev);
-    return ((uint32_t)d << 1) ^ (uint32_t)(d >> 31);
+    return lane_id() == 0 ? 0 : (int32_t)((uint32_t)q - prev);
+}
+
+// Zigzag of the Lorenzo-1 residual.
+__device__ __forceinline__ uint32_t residual_zigzag(int32_t q) { return zigzag(residual1(q)); }
+
+// Zigzagged residuals of predictors 1 (none) and 2 (Lorenzo-2) from the codes
+// q and their Lorenzo-1 residuals d1 (d1_0 = 0, so the Lorenzo-2 residual
+// d1_i - d1_(i-1) is d1_1 at lane 1 and 0 at lane 0).
+__device__ __forceinline__ void residuals_alt(int32_t q, int32_t d1, uint32_t &u_none, uint32_t &u_l2)
+{
+    uint32_t prev = wave_shift_up1((uint32_t)d1);
+    asm("" : "+v"(prev));
+    u_none = lane_id() == 0 ? 0u : zigzag(q);
+    u_l2 = zigzag((int32_t)((uint32_t)d1 - prev));
 }
 
 // Bits needed for every lane's u (0..32), uniform.
@@ -136,15 +161,32 @@ __device__ __forceinline__ void block_width2(uint32_t u, uint32_t v, uint32_t &w
     wv = ov ? 32u - (uint32_t)__builtin_clz(ov) : 0u;
 }
 
-// Codes of two blocks (the re and im planes of one amplitude block). Lane k
-// holds word k of each block in mr / mi and 0 for k at or beyond its width,
-// so both unpack in one loop up to the larger width.
+// Codes of one block from its first-order sums: d holds the zigzag-decoded
+// residuals, e their inclusive prefix sums (e_0 = 0). Predictor 0: A + e;
+// 1: the residuals themselves (A at lane 0); 2: A + the prefix sums of e (the
+// caller passes them as e2).
+__device__ __forceinline__ int32_t codes_from_sums(uint32_t pred, int32_t A, uint32_t d, uint32_t e, uint32_t e2)
+{
+    if (pred == 1) return lane_id() == 0 ? A : (int32_t)d;
+    return (int32_t)((uint32_t)A + (pred == 2 ? e2 : e));
+}
+
+// Codes of two blocks (the re and im planes of one amplitude block) from
+// their width bytes Wr / Wi. Lane k holds word k of each block in mr / mi and
+// 0 for k at or beyond its width, so both unpack in one loop up to the larger
+// width. PRED = false: the blocks are known to use predictor 0.
+template <bool PRED = true>
 __device__ __forceinline__ void unpack_codes2(uint64_t mr, uint32_t Wr, int32_t Ar, uint64_t mi, uint32_t Wi,
                                               int32_t Ai, int32_t &qr, int32_t &qi)
 {
     // planes from the most significant down: word << (63 - lane) puts this
     // lane's bit on top, and a funnel shift appends it to u
     const uint32_t up = 63u - lane_id();
+    const uint32_t Pr = PRED ? wbyte_pred(Wr) : 0u, Pi = PRED ? wbyte_pred(Wi) : 0u;
+    if (PRED) {
+        Wr = wbyte_width(Wr);
+        Wi = wbyte_width(Wi);
+    }
     const uint32_t Wm = Wr > Wi ? Wr : Wi;
     uint32_t ur = 0, ui = 0;
     for (uint32_t k = Wm; k-- > 0;) {
@@ -157,11 +199,23 @@ __device__ __forceinline__ void unpack_codes2(uint64_t mr, uint32_t Wr, int32_t 
         ur = __builtin_amdgcn_alignbit(ur, (uint32_t)(tr >> 32), 31u);
         ui = __builtin_amdgcn_alignbit(ui, (uint32_t)(ti >> 32), 31u);
     }
-    uint32_t dr = (ur >> 1) ^ (0u - (ur & 1u));
-    uint32_t di = (ui >> 1) ^ (0u - (ui & 1u));
-    if (Wm) wave_inclusive_sum2(dr, di);
-    qr = (int32_t)((uint32_t)Ar + dr);
-    qi = (int32_t)((uint32_t)Ai + di);
+    if (!PRED || (Pr | Pi) == 0) {
+        // Lorenzo-1 only: one scan in place
+        uint32_t dr = (ur >> 1) ^ (0u - (ur & 1u));
+        uint32_t di = (ui >> 1) ^ (0u - (ui & 1u));
+        if (Wm) wave_inclusive_sum2(dr, di);
+        qr = (int32_t)((uint32_t)Ar + dr);
+        qi = (int32_t)((uint32_t)Ai + di);
+        return;
+    }
+    const uint32_t dr = (ur >> 1) ^ (0u - (ur & 1u));
+    const uint32_t di = (ui >> 1) ^ (0u - (ui & 1u));
+    uint32_t er = dr, ei = di;
+    wave_inclusive_sum2(er, ei);
+    uint32_t fr = er, fi = ei;
+    if (Pr == 2 || Pi == 2) wave_inclusive_sum2(fr, fi);
+    qr = codes_from_sums(Pr, Ar, dr, er, fr);
+    qi = codes_from_sums(Pi, Ai, di, ei, fi);
 }
 
 // Four independent inclusive prefix sums, interleaved.
@@ -198,15 +252,25 @@ __device__ __forceinline__ void block_width4(const uint32_t *u_in, uint32_t *w)
     }
 }
 
-// Codes of four blocks (two amplitude blocks, both planes each), unpacked in
-// one loop up to the largest width. The words are staged in LDS:
-// stage[32 p + k] holds word k of block p (0 at or beyond its width), so each
-// plane word reaches all lanes by one broadcast LDS read instead of two
-// v_readlane. Planes go from the most significant down, as in unpack_codes2.
-__device__ __forceinline__ void unpack_codes4_lds(const uint64_t *stage, const uint32_t *W, const int32_t *A,
+// Codes of four blocks (two amplitude blocks, both planes each) from their
+// width bytes Wb, unpacked in one loop up to the largest width. The words are
+// staged in LDS: stage[32 p + k] holds word k of block p (0 at or beyond its
+// width), so each plane word reaches all lanes by one broadcast LDS read
+// instead of two v_readlane. Planes go from the most significant down, as in
+// unpack_codes2. Blocks of predictor 0 only (every block of mode 0) take one
+// scan; other predictors take a second scan (Lorenzo-2) or none (none).
+// PRED = false: the blocks are known to use predictor 0.
+template <bool PRED = true>
+__device__ __forceinline__ void unpack_codes4_lds(const uint64_t *stage, const uint32_t *Wb, const int32_t *A,
                                                   int32_t *q)
 {
     const uint32_t up = 63u - lane_id();
+    uint32_t W[4], P[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        W[p] = PRED ? wbyte_width(Wb[p]) : Wb[p];
+        P[p] = PRED ? wbyte_pred(Wb[p]) : 0u;
+    }
     const uint32_t Wm = max(max(W[0], W[1]), max(W[2], W[3]));
     uint32_t u[4] = {0u, 0u, 0u, 0u};
     for (uint32_t k = Wm; k-- > 0;) {
@@ -216,12 +280,24 @@ __device__ __forceinline__ void unpack_codes4_lds(const uint64_t *stage, const u
             u[p] = __builtin_amdgcn_alignbit(u[p], (uint32_t)(t >> 32), 31u);
         }
     }
-    uint32_t d[4];
+    if (!PRED || (P[0] | P[1] | P[2] | P[3]) == 0) {
+        // Lorenzo-1 only: one scan in place
+        uint32_t d[4];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) d[p] = (u[p] >> 1) ^ (0u - (u[p] & 1u));
-    if (Wm) wave_inclusive_sum4(d);
+        for (int p = 0; p < 4; ++p) d[p] = (u[p] >> 1) ^ (0u - (u[p] & 1u));
+        if (Wm) wave_inclusive_sum4(d);
 #pragma unroll
-    for (int p = 0; p < 4; ++p) q[p] = (int32_t)((uint32_t)A[p] + d[p]);
+        for (int p = 0; p < 4; ++p) q[p] = (int32_t)((uint32_t)A[p] + d[p]);
+        return;
+    }
+    uint32_t d[4], e[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) e[p] = d[p] = (u[p] >> 1) ^ (0u - (u[p] & 1u));
+    wave_inclusive_sum4(e);
+    uint32_t f[4] = {e[0], e[1], e[2], e[3]};
+    if (P[0] == 2 || P[1] == 2 || P[2] == 2 || P[3] == 2) wave_inclusive_sum4(f);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) q[p] = codes_from_sums(P[p], A[p], d[p], e[p], f[p]);
 }
 
 // Lane k (< W[p]) receives bit-plane word k of block p, for four blocks.
@@ -236,6 +312,33 @@ __device__ __forceinline__ void pack_planes4(const uint32_t *u, const uint32_t *
         for (int p = 0; p < 4; ++p) {
             const uint64_t bal = __builtin_amdgcn_ballot_w64(((u[p] >> k) & 1u) != 0u);
             if (lane == k) mine[p] = bal;
+        }
+    }
+}
+
+// Predictor mode 1 for two blocks: given the codes q, their Lorenzo-1
+// residuals d1 and the Lorenzo-1 zigzags u with widths W (P = 0), keep per
+// block the predictor of smallest width (ties to the lower id), updating u, W
+// and P.
+__device__ __forceinline__ void choose_predictors2(const int32_t *q, const int32_t *d1, uint32_t *u, uint32_t *W,
+                                                   uint32_t *P)
+{
+    uint32_t un[2], u2[2], wn[2], w2[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) residuals_alt(q[p], d1[p], un[p], u2[p]);
+    block_width2(un[0], un[1], wn[0], wn[1]);
+    block_width2(u2[0], u2[1], w2[0], w2[1]);
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        if (wn[p] < W[p]) {
+            W[p] = wn[p];
+            P[p] = 1;
+            u[p] = un[p];
+        }
+        if (w2[p] < W[p]) {
+            W[p] = w2[p];
+            P[p] = 2;
+            u[p] = u2[p];
         }
     }
 }

@@ -99,10 +99,11 @@ extern "C" int msv_codec_encode_static(int dtype, int log2c, double eb, const vo
     SCHK(launch_zero_words(meta, 4, s));
     SCHK(launch_zero_words((uint64_t *)kf, 1, s));
     const double inv_step = 1.0 / (2.0 * eb), step = 2.0 * eb;
-    SCHK(launch_encode_chunks(dbl, vals, nb, inv_step, W, A, slots, (double *)(meta + 3), kf + 1, step, s));
+    SCHK(launch_encode_chunks(dbl, vals, nb, inv_step, W, A, slots, (double *)(meta + 3), kf + 1, step, 0, s));
     SCHK(launch_scan_chunks(W, A, nb, 1, off, meta, kf, kf + 1, s));
     SCHK(launch_scan_sizes(meta, 1, meta + 1, s));
-    SCHK(launch_assemble_chunks(dbl ? 0 : 1, log2c, eb, W, A, nullptr, slots, off, meta, kf, meta + 1, 1, out, s));
+    SCHK(launch_assemble_chunks(dbl ? 0 : 1, log2c, eb, 0, W, A, nullptr, slots, off, meta, kf, meta + 1, 1, out,
+                                s));
     uint64_t hmeta[4];
     uint32_t hkf[2];
     SCHK(hipMemcpyAsync(hmeta, meta, 32, hipMemcpyDeviceToHost, s));

@@ -11,8 +11,8 @@
 // such a group crosses the host link.
 //
 // This is the library's own CPU implementation of the chunk format (block by
-// block, bit planes packed a word at a time); it shares nothing with the test
-// oracle.
+// block, bit planes packed a word at a time, the three predictors of the
+// width byte); it shares nothing with the test oracle.
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -44,26 +44,36 @@ bool decode_chunk(const uint8_t *p, uint64_t bytes, int log2c, double step, cpx 
         for (uint64_t i = 0; i < C; ++i) out[i] = 0.0;
         return true;
     }
+    uint32_t mode;
+    memcpy(&mode, p + 28, 4);
+    if (mode > 1) return false;
     const uint8_t *W = p + 32;
     const int32_t *A = (const int32_t *)(p + 32 + pad8(nb));
     const uint64_t *pay = (const uint64_t *)(p + 32 + pad8(nb) + pad8(4 * nb));
     uint64_t words = 0;
     for (uint64_t b = 0; b < nb; ++b) {
-        if (W[b] > 32) return false;
-        words += W[b];
+        if ((W[b] & 63) > 32 || (W[b] >> 6) > (mode ? 2 : 0)) return false;
+        words += W[b] & 63;
     }
     if (32 + pad8(nb) + pad8(4 * nb) + 8 * words != bytes) return false;
     uint64_t off = 0;
     for (uint64_t b = 0; b < nb; ++b) {
         const uint64_t j = b >> 1, plane = b & 1;
-        const uint32_t w = W[b];
-        int32_t q = A[b];
+        const uint32_t w = W[b] & 63, pred = W[b] >> 6;
+        uint32_t q = (uint32_t)A[b], e = 0;   // code and first difference, mod 2^32
         for (int i = 0; i < 64; ++i) {
             uint32_t u = 0;
             for (uint32_t k = 0; k < w; ++k) u |= (uint32_t)((pay[off + k] >> i) & 1ull) << k;
-            const int32_t d = (int32_t)(u >> 1) ^ -(int32_t)(u & 1u);   // zigzag inverse
-            if (i > 0) q += d;
-            const T x = (T)((double)q * step);
+            const uint32_t d = (u >> 1) ^ (0u - (u & 1u));   // zigzag inverse
+            if (i > 0) {
+                if (pred == 0) q += d;
+                else if (pred == 1) q = d;
+                else {
+                    e += d;
+                    q += e;
+                }
+            }
+            const T x = (T)((double)(int32_t)q * step);
             cpx &o = out[j * 64 + (uint64_t)i];
             o = plane ? cpx(o.real(), (double)x) : cpx((double)x, o.imag());
         }
@@ -77,11 +87,30 @@ struct EncodeStats {
     bool bad = false;
 };
 
+// Zigzagged residuals of one block's codes under predictor pred (u[0] = 0)
+// and their width.
+uint32_t block_residuals(const int32_t *q, uint32_t pred, uint32_t *u)
+{
+    uint32_t any = 0;
+    u[0] = 0;
+    for (int i = 1; i < 64; ++i) {
+        uint32_t d;
+        if (pred == 0) d = (uint32_t)q[i] - (uint32_t)q[i - 1];
+        else if (pred == 1) d = (uint32_t)q[i];
+        else if (i == 1) d = (uint32_t)q[1] - (uint32_t)q[0];
+        else d = (uint32_t)q[i] - 2u * (uint32_t)q[i - 1] + (uint32_t)q[i - 2];
+        u[i] = (d << 1) ^ (0u - (d >> 31));
+        any |= u[i];
+    }
+    return any ? 32u - (uint32_t)__builtin_clz(any) : 0u;
+}
+
 // Encode C = 2^log2c values (rounded to T first) as a canonical chunk into
-// out (capacity: the chunk bound); returns its size.
+// out (capacity: the chunk bound) in predictor mode pred_mode; returns its
+// size.
 template <typename T>
-uint64_t encode_chunk(const cpx *v, int log2c, int dtype, double eb, double inv_step, double step, uint8_t *out,
-                      EncodeStats &st)
+uint64_t encode_chunk(const cpx *v, int log2c, int dtype, double eb, double inv_step, double step, int pred_mode,
+                      uint8_t *out, EncodeStats &st)
 {
     const uint64_t C = 1ull << log2c, nb = 2 * C / 64;
     uint8_t *W = out + 32;
@@ -93,7 +122,7 @@ uint64_t encode_chunk(const cpx *v, int log2c, int dtype, double eb, double inv_
     for (uint64_t b = 0; b < nb; ++b) {
         const uint64_t j = b >> 1, plane = b & 1;
         int32_t q[64];
-        uint32_t u[64], any = 0;
+        uint32_t u[64];
         for (int i = 0; i < 64; ++i) {
             const cpx &c = v[j * 64 + (uint64_t)i];
             const T x = (T)(plane ? c.imag() : c.real());
@@ -109,13 +138,18 @@ uint64_t encode_chunk(const cpx *v, int log2c, int dtype, double eb, double inv_
             const T xr = (T)((double)q[i] * step);
             st.err = std::max(st.err, (double)std::fabs(x - xr));
         }
-        for (int i = 0; i < 64; ++i) {
-            const int32_t d = i ? q[i] - q[i - 1] : 0;
-            u[i] = ((uint32_t)d << 1) ^ (uint32_t)(d >> 31);
-            any |= u[i];
+        uint32_t w = block_residuals(q, 0, u), pred = 0;
+        if (pred_mode) {
+            for (uint32_t p = 1; p <= 2; ++p) {
+                const uint32_t wp = block_residuals(q, p, u);
+                if (wp < w) {
+                    w = wp;
+                    pred = p;
+                }
+            }
+            block_residuals(q, pred, u);
         }
-        const uint32_t w = any ? 32u - (uint32_t)__builtin_clz(any) : 0u;
-        W[b] = (uint8_t)w;
+        W[b] = (uint8_t)(w | (pred << 6));
         A[b] = q[0];
         if (w || q[0]) zero = false;
         for (uint32_t k = 0; k < w; ++k) {
@@ -127,7 +161,7 @@ uint64_t encode_chunk(const cpx *v, int log2c, int dtype, double eb, double inv_
     }
     st.words += (double)off;
     const uint64_t total = zero ? 32 : 32 + pad8(nb) + pad8(4 * nb) + 8 * off;
-    const uint32_t magic = kMagic, nbl = (uint32_t)nb, zero32 = 0;
+    const uint32_t magic = kMagic, nbl = (uint32_t)nb, mode32 = (uint32_t)pred_mode;
     memcpy(out, &magic, 4);
     out[4] = 1;
     out[5] = zero ? 0 : 1;
@@ -136,7 +170,7 @@ uint64_t encode_chunk(const cpx *v, int log2c, int dtype, double eb, double inv_
     memcpy(out + 8, &eb, 8);
     memcpy(out + 16, &total, 8);
     memcpy(out + 24, &nbl, 4);
-    memcpy(out + 28, &zero32, 4);
+    memcpy(out + 28, &mode32, 4);
     return total;
 }
 
@@ -235,7 +269,7 @@ int run_group(msv_sim *s, const Pass &pass, const std::vector<uint64_t> &chunks,
     std::vector<uint8_t> buf(32 + pad8(nb) + pad8(4 * nb) + 8 * 32 * nb);
     for (size_t k = 0; k < chunks.size(); ++k) {
         const uint64_t bytes = encode_chunk<T>(a.data() + k * C, c, s->is_double() ? 0 : 1, s->eb, s->inv_step(),
-                                               s->step(), buf.data(), st);
+                                               s->step(), s->pred_mode, buf.data(), st);
         uint64_t pos = 0;
         int e = host_arena_alloc(s, out_side, bytes, &pos);   // serialised inside
         if (e) return e;

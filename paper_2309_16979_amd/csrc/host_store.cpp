@@ -283,7 +283,7 @@ int compact_batch(msv_sim *s, BatchBufs &b, uint64_t n, const uint32_t *src_off,
     HIPCHK(s, launch_scan_chunks((const uint8_t *)b.out_W.p, (const int32_t *)b.out_A.p, nb, n,
                                  (uint32_t *)b.dst_off.p, v.sizes, v.kinds, v.flags, cs));
     HIPCHK(s, launch_scan_sizes(v.sizes, n, v.offsets, cs));
-    HIPCHK(s, launch_assemble_chunks(s->is_double() ? 0 : 1, s->log2c, s->eb, (const uint8_t *)b.out_W.p,
+    HIPCHK(s, launch_assemble_chunks(s->is_double() ? 0 : 1, s->log2c, s->eb, s->pred_mode, (const uint8_t *)b.out_W.p,
                                      (const int32_t *)b.out_A.p, src_off, src_heap, (const uint32_t *)b.dst_off.p,
                                      v.sizes, v.kinds, v.offsets, n, (uint8_t *)b.out_stage.p, cs));
     uint64_t *pm = (uint64_t *)b.pin_meta.p;
@@ -325,7 +325,7 @@ int encode_plain_chunks(msv_sim *s, const void *vals, uint64_t c0, uint64_t m, i
     MetaView v = meta_view(s, b);
     HIPCHK(s, launch_encode_chunks(s->is_double(), vals, m * nb, s->inv_step(), (uint8_t *)b.out_W.p,
                                    (int32_t *)b.out_A.p, (uint64_t *)b.out_heap.p, (double *)(v.flags + 2),
-                                   v.flags, s->step(), cs));
+                                   v.flags, s->step(), s->pred_mode, cs));
     int st;
     if ((st = compact_batch(s, b, m, nullptr, (const uint64_t *)b.out_heap.p))) return st;
     HIPCHK(s, hipEventRecord(b.k_done, cs));
@@ -424,6 +424,7 @@ int init_host_store_state(msv_sim *s, const void *host)
 
 int apply_host_store(msv_sim *s, const std::vector<Prim> &prims, size_t n_gates)
 {
+    if (s->pred_mode) s->pred_used = true;   // this call's encodes may choose other predictors
     (void)n_gates;
     HostStore &h = s->hs;
     hipStream_t cs = s->stream();
@@ -589,6 +590,8 @@ int apply_host_store(msv_sim *s, const std::vector<Prim> &prims, size_t n_gates)
             pb.part = (double *)h.part.p + 3 * g.tile_begin;
             pb.flags = v.flags;
             pb.check_err = s->check_bound;
+            pb.pred_mode = s->pred_mode;
+            pb.in_pred = s->in_pred();
             pb.ops = (const OpDesc *)s->ws.ops.p;
             pb.pool = s->ws.pool.p;
             HIPCHK(s, launch_pass(s->is_double(), true, true, g, pb, cs));
@@ -715,7 +718,7 @@ int host_store_decode_range(msv_sim *s, uint64_t first, uint64_t count, void *de
         const uint64_t c1 = std::min(((first + count - 1) >> s->log2c) + 1, c0 + K);
         if ((st = stage_range(s, c0, c1 - c0))) return st;
         const uint64_t hi = std::min(first + count, c1 * C);
-        HIPCHK(s, launch_decode_range(s->is_double(), true, nullptr, staged_view(s), s->step(), s->scale, a, hi - a,
+        HIPCHK(s, launch_decode_range(s->is_double(), s->decode_comp(), nullptr, staged_view(s), s->step(), s->scale, a, hi - a,
                                       (uint8_t *)dev_out + s->elt() * (a - first), s->stream()));
         HIPCHK(s, hipStreamSynchronize(s->stream()));
         a = hi;
@@ -743,7 +746,7 @@ int host_store_reduce(msv_sim *s, ReduceArgs a, int *groups)
         if (ref0) b.ref = ref0 + 2 * (x - a.amp_begin);
         // the reduce kernel indexes ref relative to its own amp_begin
         int g = 0;
-        HIPCHK(s, launch_reduce(s->is_double(), true, nullptr, staged_view(s), s->step(), b, &g, s->stream()));
+        HIPCHK(s, launch_reduce(s->is_double(), s->decode_comp(), nullptr, staged_view(s), s->step(), b, &g, s->stream()));
         HIPCHK(s, hipStreamSynchronize(s->stream()));
         total += g;
         x = hi;

@@ -32,6 +32,8 @@ struct PassBuffers {
                                  // payload words written (3 doubles)
     uint32_t *flags;             // bit 0: code out of range / non-finite value
     int32_t check_err;
+    int32_t pred_mode;           // encode: 0 Lorenzo-1 for every block, 1 per-block choice
+    int32_t in_pred;             // compressed input may carry predictors other than 0
     const OpDesc *ops;
     const void *pool;            // matrix pool, complex of the state's real type
     const uint64_t *obs_masks;   // OP_OBS: Z masks and coefficients
@@ -112,7 +114,9 @@ struct ReduceArgs {
 
 // Per-workgroup partials of an FP64 reduction over decoded amplitudes.
 // Returns the number of workgroups used.
-hipError_t launch_reduce(bool is_double, bool compressed, const void *amps, BlockStore st,
+// comp: 0 plain amplitudes, 1 block store of predictor-0 blocks only, 2 block
+// store whose blocks may use any predictor.
+hipError_t launch_reduce(bool is_double, int comp, const void *amps, BlockStore st,
                          double step, const ReduceArgs &a, int *n_groups, hipStream_t stream);
 // out[j] = sum_g partials[4 g + j] (fixed order), j < 4.
 hipError_t launch_reduce_final(const double *partials, int n_groups, double *out,
@@ -124,8 +128,9 @@ hipError_t launch_pass_stats(const double *part, const uint64_t *pass_offsets, i
                              double *out, hipStream_t stream);
 
 // Decode amplitudes [amp_begin, amp_begin + amp_count) (multiples of 64) into
-// out, times scale: from the block store (compressed) or the plain amplitudes.
-hipError_t launch_decode_range(bool is_double, bool compressed, const void *amps, BlockStore st, double step,
+// out, times scale: from the block store (comp 1 or 2, as for launch_reduce)
+// or the plain amplitudes (comp 0).
+hipError_t launch_decode_range(bool is_double, int comp, const void *amps, BlockStore st, double step,
                                double scale, uint64_t amp_begin, uint64_t amp_count, void *out,
                                hipStream_t stream);
 
@@ -136,15 +141,18 @@ hipError_t launch_zero_words(uint64_t *p, uint64_t n_words, hipStream_t stream);
 // ---- canonical chunk format (codec API, export, host store) ----------------
 
 // Encode n_chunks chunks of interleaved complex values (contiguous) into
-// per-block slots: W[b], A[b], and payload words at slot_words[b * 32].
+// per-block slots: width byte W[b] (width | predictor << 6), A[b], and payload
+// words at slot_words[b * 32]. pred_mode 0: Lorenzo-1 for every block; 1: per
+// block the predictor of smallest width.
 hipError_t launch_encode_chunks(bool is_double, const void *vals, uint64_t n_blocks_total,
                                 double inv_step, uint8_t *W, int32_t *A, uint64_t *slot_words,
-                                double *err_max_bits, uint32_t *flags, double step,
+                                double *err_max_bits, uint32_t *flags, double step, int pred_mode,
                                 hipStream_t stream);
 
-// Per chunk c (n_chunks of nb blocks): exclusive scan of W into off[] (words,
-// relative to the chunk payload start) and the canonical chunk size in
-// sizes[c]; kinds[c] = 0 when every W and A is zero. flags bit 1 = a W > 32.
+// Per chunk c (n_chunks of nb blocks): exclusive scan of the widths of the
+// width bytes W into off[] (words, relative to the chunk payload start) and
+// the canonical chunk size in sizes[c]; kinds[c] = 0 when every W and A is
+// zero. flags bit 1 = a width above 32 or a predictor above 2.
 hipError_t launch_scan_chunks(const uint8_t *W, const int32_t *A, uint64_t nb, uint64_t n_chunks,
                               uint32_t *off, uint64_t *sizes, uint32_t *kinds, uint32_t *flags,
                               hipStream_t stream);
@@ -153,10 +161,11 @@ hipError_t launch_scan_chunks(const uint8_t *W, const int32_t *A, uint64_t nb, u
 hipError_t launch_scan_sizes(const uint64_t *sizes, uint64_t n, uint64_t *offsets,
                              hipStream_t stream);
 
-// Write canonical chunks: header, W, A and payload copied from src_heap at
-// src_off[b] (words; nullptr = per-block slots of 32 words) for each block.
-// Chunk c goes to out + offsets[c] (offsets 256-byte aligned).
-hipError_t launch_assemble_chunks(int dtype, int log2c, double eb, const uint8_t *W,
+// Write canonical chunks: header (mode field = pred_mode), W, A and payload
+// copied from src_heap at src_off[b] (words; nullptr = per-block slots of 32
+// words) for each block. Chunk c goes to out + offsets[c] (offsets 256-byte
+// aligned).
+hipError_t launch_assemble_chunks(int dtype, int log2c, double eb, int pred_mode, const uint8_t *W,
                                   const int32_t *A, const uint32_t *src_off,
                                   const uint64_t *src_heap, const uint32_t *dst_off,
                                   const uint64_t *sizes, const uint32_t *kinds,
@@ -165,8 +174,9 @@ hipError_t launch_assemble_chunks(int dtype, int log2c, double eb, const uint8_t
 
 // Parse staged canonical chunks (chunk c at base + offsets[c], staged[c]
 // bytes, offsets 8-byte aligned) into W/A/OFF arrays of slot c (OFF relative to
-// base, in words). A chunk whose header, widths or length disagree is read as
-// all zeros and sets flags bit 2; nothing beyond staged[c] bytes is read.
+// base, in words). A chunk whose header, width bytes (for the header's
+// predictor mode) or length disagree is read as all zeros and sets flags bit 2;
+// nothing beyond staged[c] bytes is read.
 hipError_t launch_parse_chunks(const uint8_t *base, const uint64_t *offsets, const uint64_t *staged,
                                uint64_t n_chunks, int log2c, uint8_t *W, int32_t *A, uint32_t *OFF,
                                uint32_t *flags, hipStream_t stream);

@@ -22,7 +22,7 @@ namespace msv {
 // One tile of a pass: decode -> ops -> encode, then the workgroup's FP64
 // statistics into part[3 pidx ..]. Shared by the single-state pass kernel and
 // the batched kernel.
-template <typename T, int TB, bool LOADC, bool STOREC, int KMAX, int MF>
+template <typename T, int TB, bool LOADC, bool STOREC, int KMAX, int MF, bool PRED>
 __device__ __forceinline__ void pass_tile(const PassGeom &geo, const PassBuffers &buf, uint64_t tile, uint64_t pidx)
 {
     constexpr int TILE = 1 << TB;
@@ -52,7 +52,7 @@ __device__ __forceinline__ void pass_tile(const PassGeom &geo, const PassBuffers
     __syncthreads();
 
     const double sc = buf.scale_src ? 1.0 / __builtin_sqrt(*buf.scale_src) : buf.scale;
-    tile_load<T, TB, LOADC>(sre, sim, sG, buf.amps_in, buf.in, buf.step, sc, wave, lane, sx + 128 * wave);
+    tile_load<T, TB, LOADC, PRED>(sre, sim, sG, buf.amps_in, buf.in, buf.step, sc, wave, lane, sx + 128 * wave);
     __syncthreads();
 
     const T *pool = (const T *)buf.pool;
@@ -86,8 +86,8 @@ __device__ __forceinline__ void pass_tile(const PassGeom &geo, const PassBuffers
     double nrm = 0.0, err = 0.0;
     const uint64_t slot = (tile - buf.slot_tile0) * (uint64_t)(32 * NSB);
     static_assert(NSB <= 256, "per-wave offsets hold 256 words");
-    const uint32_t words = tile_store<T, TB, STOREC, true>(sre, sim, sG, sW, sA, sOff, buf.amps_out, buf.out, slot,
-                                                           buf.inv_step, buf.step, buf.check_err, buf.flags, nrm,
+    const uint32_t words = tile_store<T, TB, STOREC, true, PRED>(sre, sim, sG, sW, sA, sOff, buf.amps_out, buf.out, slot,
+                                                           buf.inv_step, buf.step, buf.check_err, buf.pred_mode, buf.flags, nrm,
                                                            err, wave, lane,
                                                            reinterpret_cast<uint32_t *>(sx + 128 * wave));
     // per-workgroup statistics (fixed reduction order)
@@ -109,10 +109,13 @@ __device__ __forceinline__ void pass_tile(const PassGeom &geo, const PassBuffers
 // workgroups of 2^12 complex64 amplitudes per CU), two for the rest.
 template <int TB, int KMAX> struct PassOccupancy { static constexpr int waves = (KMAX <= 3 && TB <= 12) ? 4 : 2; };
 
-template <typename T, int TB, bool LOADC, bool STOREC, int KMAX, int MF>
+// PRED: the decode reads predictor ids and the encode carries predictor mode 1
+// (buf.pred_mode). Variants without it assume predictor 0 throughout and are
+// launched only when buf.pred_mode and buf.in_pred are both 0.
+template <typename T, int TB, bool LOADC, bool STOREC, int KMAX, int MF, bool PRED>
 __global__ __launch_bounds__(kThreads, (PassOccupancy<TB, KMAX>::waves)) void pass_kernel(PassGeom geo, PassBuffers buf)
 {
-    pass_tile<T, TB, LOADC, STOREC, KMAX, MF>(geo, buf, geo.tile_begin + blockIdx.x, blockIdx.x);
+    pass_tile<T, TB, LOADC, STOREC, KMAX, MF, PRED>(geo, buf, geo.tile_begin + blockIdx.x, blockIdx.x);
 }
 
 template <typename T, int TB, int KMAX, int MF>
@@ -120,14 +123,21 @@ static hipError_t launch_k(bool load_c, bool store_c, const PassGeom &geo, const
                            hipStream_t stream)
 {
     const dim3 grid((unsigned)geo.n_tiles), block(kThreads);
-    if (load_c && store_c)
-        hipLaunchKernelGGL((pass_kernel<T, TB, true, true, KMAX, MF>), grid, block, 0, stream, geo, buf);
+    const bool pred = (store_c && buf.pred_mode != 0) || (load_c && buf.in_pred != 0);
+    if (load_c && store_c && pred)
+        hipLaunchKernelGGL((pass_kernel<T, TB, true, true, KMAX, MF, true>), grid, block, 0, stream, geo, buf);
+    else if (load_c && store_c)
+        hipLaunchKernelGGL((pass_kernel<T, TB, true, true, KMAX, MF, false>), grid, block, 0, stream, geo, buf);
+    else if (load_c && pred)
+        hipLaunchKernelGGL((pass_kernel<T, TB, true, false, KMAX, MF, true>), grid, block, 0, stream, geo, buf);
     else if (load_c)
-        hipLaunchKernelGGL((pass_kernel<T, TB, true, false, KMAX, MF>), grid, block, 0, stream, geo, buf);
+        hipLaunchKernelGGL((pass_kernel<T, TB, true, false, KMAX, MF, false>), grid, block, 0, stream, geo, buf);
+    else if (store_c && pred)
+        hipLaunchKernelGGL((pass_kernel<T, TB, false, true, KMAX, MF, true>), grid, block, 0, stream, geo, buf);
     else if (store_c)
-        hipLaunchKernelGGL((pass_kernel<T, TB, false, true, KMAX, MF>), grid, block, 0, stream, geo, buf);
+        hipLaunchKernelGGL((pass_kernel<T, TB, false, true, KMAX, MF, false>), grid, block, 0, stream, geo, buf);
     else
-        hipLaunchKernelGGL((pass_kernel<T, TB, false, false, KMAX, MF>), grid, block, 0, stream, geo, buf);
+        hipLaunchKernelGGL((pass_kernel<T, TB, false, false, KMAX, MF, false>), grid, block, 0, stream, geo, buf);
     return hipGetLastError();
 }
 

@@ -89,6 +89,15 @@ struct msv_sim {
     int lookahead = 1024;
     int segments = 1;                // register segments in pass kernels
     int relabel = 1;                 // SWAPs of block-index qubits as relabelling (compressed device store)
+    int pred_mode = 0;               // codec predictor mode of every encode (option "predictor")
+    bool pred_used = false;          // a block of the current state may carry a predictor other than 0
+    // predictor mode written into chunk headers assembled from the current state
+    int export_pred_mode() const { return (pred_mode || pred_used) ? 1 : 0; }
+    // stored blocks may carry a predictor other than 0 (decoders must read it)
+    int in_pred() const { return (pred_mode || pred_used) ? 1 : 0; }
+    // kind of decode for reductions and read-outs: 0 plain, 1 predictor-0
+    // blocks only, 2 any predictor
+    int decode_comp() const { return eb > 0.0 ? (in_pred() ? 2 : 1) : 0; }
     int tuned_k = 0, tuned_tb = 0;   // last autotuner choice
     // Offline-stage result of the last device-store msv_apply: the passes and
     // their lowered descriptors, reused when the next call brings the same

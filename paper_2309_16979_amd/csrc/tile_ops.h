@@ -97,8 +97,9 @@ __device__ __forceinline__ void tile_blocks(const PassGeom &geo, uint64_t base, 
 // ------------------------------------------------------------------ load
 
 // stage: 128 words of LDS for this wave, through which the compressed decode
-// broadcasts plane words (unpack_codes4_lds).
-template <typename T, int TB, bool LOADC>
+// broadcasts plane words (unpack_codes4_lds). PRED = false: every block of
+// the input uses predictor 0.
+template <typename T, int TB, bool LOADC, bool PRED = true>
 __device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, const void *amps, const BlockStore &in,
                                           double step, double sc, int wave, int lane, uint64_t *stage)
 {
@@ -151,7 +152,8 @@ __device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, co
         uint64_t mine[2 * RA];
 #pragma unroll
         for (int j = 0; j < 2 * RA; ++j) {
-            const uint32_t W = (uint32_t)__builtin_amdgcn_readlane((int)wv, j);
+            const uint32_t wj = (uint32_t)__builtin_amdgcn_readlane((int)wv, j);
+            const uint32_t W = PRED ? wbyte_width(wj) : wj;   // without PRED the byte is the width
             const uint32_t off = (uint32_t)__builtin_amdgcn_readlane((int)ov, j);
             mine[j] = 0;
             if ((uint32_t)lane < W) mine[j] = in.heap[(uint64_t)off + lane];
@@ -172,7 +174,7 @@ __device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, co
 #pragma unroll
                     for (int p = 0; p < 4; ++p) stage[32 * p + lane] = mine[2 * a + p];
                 }
-                unpack_codes4_lds(stage, W4, A4, q4);
+                unpack_codes4_lds<PRED>(stage, W4, A4, q4);
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     T xr = dequantize<T>(q4[2 * h], step), xi = dequantize<T>(q4[2 * h + 1], step);
@@ -189,7 +191,7 @@ __device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, co
                 const int jb = wave + NW * (r0 + a);
                 if (r0 + a >= APW || jb >= NAB) break;
                 int32_t qr, qi;
-                unpack_codes2(mine[2 * a], (uint32_t)__builtin_amdgcn_readlane((int)wv, 2 * a),
+                unpack_codes2<PRED>(mine[2 * a], (uint32_t)__builtin_amdgcn_readlane((int)wv, 2 * a),
                               __builtin_amdgcn_readlane(av, 2 * a), mine[2 * a + 1],
                               (uint32_t)__builtin_amdgcn_readlane((int)wv, 2 * a + 1),
                               __builtin_amdgcn_readlane(av, 2 * a + 1), qr, qi);
@@ -206,16 +208,50 @@ __device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, co
 
 // ----------------------------------------------------------------- store
 
+// Predictor mode 1 for one block held as Lorenzo-1 zigzags (*u_p, this
+// lane's value) with width byte *w_p and anchor A: the codes come back as A
+// plus the prefix sums of the residuals; when predictor 1 or 2 needs fewer
+// bits, its zigzags replace *u_p and *w_p becomes width | predictor << 8
+// (lane 0 writes it).
+__device__ __forceinline__ void repredict(uint32_t *u_p, uint32_t *w_p, int32_t A, int lane)
+{
+    const uint32_t u = *u_p;
+    const uint32_t d = (u >> 1) ^ (0u - (u & 1u));
+    const int32_t q = (int32_t)((uint32_t)A + wave_inclusive_sum(d));
+    uint32_t un, u2;
+    residuals_alt(q, (int32_t)d, un, u2);
+    const uint32_t w1 = *w_p, wn = block_width(un), w2 = block_width(u2);
+    uint32_t w = w1, pred = 0, best = u;
+    if (wn < w) {
+        w = wn;
+        pred = 1;
+        best = un;
+    }
+    if (w2 < w) {
+        w = w2;
+        pred = 2;
+        best = u2;
+    }
+    if (pred) {
+        *u_p = best;
+        if (lane == 0) *w_p = w | (pred << 8);
+    }
+}
+
 // Store the tile (plain or encoded). nrm / err accumulate this thread's FP64
 // sum |x|^2 and max |x - x'|; the return value is the tile's payload words
-// (valid in every thread). The codec scratch sW / sA / sOff holds NSB entries.
+// (valid in every thread). The codec scratch sW / sA / sOff holds NSB entries;
+// sW holds width | predictor << 8. pred_mode 0: Lorenzo-1 for every block;
+// 1: per block the predictor of smallest width (compiled in when PRED; the
+// variants without it keep the register budget of the Lorenzo-1 path).
 // OWN_OFF: `own_off` (2^(TB-5) words of LDS for this wave) receives the
 // payload offsets: every wave scans the widths itself (E2), so E3 needs no
 // second barrier. Otherwise wave 0 scans into sOff.
-template <typename T, int TB, bool STOREC, bool OWN_OFF = false>
+template <typename T, int TB, bool STOREC, bool OWN_OFF = false, bool PRED = true>
 __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *sG, uint32_t *sW, int32_t *sA,
                                                uint32_t *sOff, void *amps, const BlockStore &out, uint64_t slot,
-                                               double inv_step, double step, int check, uint32_t *flags,
+                                               double inv_step, double step, int check, int pred_mode,
+                                               uint32_t *flags,
                                                double &nrm, double &err, int wave, int lane,
                                                uint32_t *own_off = nullptr)
 {
@@ -310,6 +346,20 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
             sA[2 * jb + 1] = Ai;
         }
     }
+    // E1b (predictor mode 1): each wave revisits its own blocks; the codes come
+    // back from the Lorenzo-1 zigzags in LDS (prefix sums from the anchor), the
+    // other two predictors' residuals and widths are formed, and a block whose
+    // width shrinks takes the better predictor (ties to the lower id)
+    if (PRED && pred_mode) {
+#pragma unroll 1
+        for (int jb = wave; jb < NAB; jb += NW) {
+            const int l = swz(jb * 64 + lane);
+            uint32_t *ur_p = reinterpret_cast<uint32_t *>(sre) + l * VPT;
+            uint32_t *ui_p = reinterpret_cast<uint32_t *>(sim) + l * VPT;
+            repredict(ur_p, sW + 2 * jb, sA[2 * jb], lane);
+            repredict(ui_p, sW + 2 * jb + 1, sA[2 * jb + 1], lane);
+        }
+    }
     err = fmax(err, (double)errt);
     if (bad) atomicOr(flags, 1u);
     __syncthreads();
@@ -322,7 +372,7 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int idx = lane * PER + i;
-            v[i] = idx < NSB ? sW[idx] : 0u;
+            v[i] = idx < NSB ? (PRED ? sW[idx] & 0xffu : sW[idx]) : 0u;
             s += v[i];
         }
         uint32_t ex = wave_inclusive_sum(s) - s;
@@ -344,7 +394,8 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
                                    reinterpret_cast<const uint32_t *>(sim)[l0 * VPT],
                                    reinterpret_cast<const uint32_t *>(sre)[l1 * VPT],
                                    reinterpret_cast<const uint32_t *>(sim)[l1 * VPT]};
-            const uint32_t W4[4] = {sW[2 * jb], sW[2 * jb + 1], sW[2 * jc], sW[2 * jc + 1]};
+            constexpr uint32_t WM = PRED ? 0xffu : ~0u;   // without PRED sW holds the width alone
+            const uint32_t W4[4] = {sW[2 * jb] & WM, sW[2 * jb + 1] & WM, sW[2 * jc] & WM, sW[2 * jc + 1] & WM};
             uint64_t m[4];
             pack_planes4(u, W4, m);
             const uint32_t o4[4] = {so[2 * jb], so[2 * jb + 1], so[2 * jc], so[2 * jc + 1]};
@@ -357,7 +408,8 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
             const int l = swz(jb * 64 + lane);
             const uint32_t ur = reinterpret_cast<const uint32_t *>(sre)[l * VPT];
             const uint32_t ui = reinterpret_cast<const uint32_t *>(sim)[l * VPT];
-            const uint32_t Wr = sW[2 * jb], Wi = sW[2 * jb + 1];
+            constexpr uint32_t WM = PRED ? 0xffu : ~0u;
+            const uint32_t Wr = sW[2 * jb] & WM, Wi = sW[2 * jb + 1] & WM;
             const uint64_t mr = pack_planes(ur, Wr);
             const uint64_t mi = pack_planes(ui, Wi);
             if ((uint32_t)lane < Wr) out.heap[slot + so[2 * jb] + lane] = mr;
@@ -371,12 +423,12 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
         if (j < 2 * APW && jb < NAB) {
             const int bt = 2 * jb + (j & 1);
             const uint64_t bi = block_index(out, 2 * sG[jb] + (uint64_t)(j & 1));
-            out.W[bi] = (uint8_t)sW[bt];
+            out.W[bi] = PRED ? (uint8_t)((sW[bt] & 63u) | ((sW[bt] >> 8) << 6)) : (uint8_t)sW[bt];
             out.A[bi] = sA[bt];
             out.OFF[bi] = (uint32_t)(slot + so[bt]);
         }
     }
-    return so[NSB - 1] + sW[NSB - 1];
+    return so[NSB - 1] + (PRED ? sW[NSB - 1] & 0xffu : sW[NSB - 1]);
 }
 
 // ------------------------------------------------------------------- ops

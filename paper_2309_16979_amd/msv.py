@@ -243,8 +243,9 @@ def codec_bound(log2c: int) -> int:
     return int(load().msv_codec_bound(log2c))
 
 
-def codec_encode(values: np.ndarray, log2c: int, eb: float) -> bytes:
-    """Encode one chunk on the GPU (format MSVC v1)."""
+def codec_encode(values: np.ndarray, log2c: int, eb: float, mode: int = 0) -> bytes:
+    """Encode one chunk on the GPU (format MSVC v1; mode 0: Lorenzo-1 for every
+    block, mode 1: per-block predictor choice)."""
     v = np.ascontiguousarray(values)
     dt = {np.dtype(np.complex128): L.C128, np.dtype(np.complex64): L.C64}[v.dtype]
     if v.size != 1 << log2c:
@@ -252,7 +253,8 @@ def codec_encode(values: np.ndarray, log2c: int, eb: float) -> bytes:
     cap = codec_bound(log2c)
     out = np.zeros(cap, dtype=np.uint8)
     n = C.c_size_t(0)
-    check(load().msv_codec_encode(dt, log2c, float(eb), v.ctypes.data, out.ctypes.data, cap, C.byref(n)))
+    check(load().msv_codec_encode_mode(dt, log2c, float(eb), int(mode), v.ctypes.data, out.ctypes.data, cap,
+                                       C.byref(n)))
     return out[: n.value].tobytes()
 
 
