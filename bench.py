@@ -550,7 +550,9 @@ def bench_batch256(a):
            "data": "synthetic: seeded random circuits",
            "config": {"workload": "256 circuits n in [12,24], depth 10..60, complex64, eb=1e-4, autotuned",
                       "circuits": 256, "updates": upd},
-           "s_per_batch": dt, "kernel_launches": st["kernel_launches"], "passes": st["passes"]}
+           "s_per_batch": dt, "kernel_launches": st["kernel_launches"], "passes": st["passes"],
+           "kernel_s": st["t_kernel"], "note": "s_per_batch is the whole call: simulators, planning (cost-model "
+           "search on the host), upload, the persistent launch and read-back; kernel_s is the launch alone"}
     n, layers, sets = 18, 6, 64
     gates = ansatz(n, layers)
     P = ansatz_params(n, layers, seed=a.seed, count=sets)

@@ -406,9 +406,18 @@ int msv_batch_run(const msv_circuit *circuits, size_t count, int dtype, double e
  * fixed table of autotune mode 1 came from this call on an MI355X. */
 int msv_autotune_calibrate(int dtype, double *model, size_t cap);
 /* Adjoint gradients of one ansatz for n_sets parameter sets (params is
- * n_sets x n_params, row-major); expvals[n_sets], grads[n_sets x n_params].
- * Sets run on up to 8 concurrent workers, each with its own simulator and
- * stream (as msv_adjoint on a fresh state). */
+ * n_sets x n_params, row-major); expvals[n_sets], grads[n_sets x n_params];
+ * each set starts from |ansatz->init_basis>, as msv_adjoint on a fresh state.
+ * Every set's passes are work items of shared persistent launches: one
+ * launch for the forward sweeps and lambda = O psi, one reduction for the
+ * expectations, then per checkpoint segment (last first) one launch that
+ * recomputes psi over the segment (all but the last) and one launch of its
+ * two-state reverse passes, then one launch summing the gradients: the
+ * launch count depends on the segments, not on n_sets. Checkpoints (gate
+ * indices in (0, n_gates)) are kept as full block stores here, not in the
+ * canonical chunk format. ansatz->n_qubits in [8, 30]; eb = 0 runs on plain
+ * amplitudes. MSV_E_RANGE if a value leaves the codec range, MSV_E_DEVICE if
+ * a dependency wait of the work queue exceeds its limit. */
 int msv_batch_adjoint(const msv_circuit *ansatz, const double *params, size_t n_sets,
                       size_t n_params, const uint64_t *z_masks, const double *coeffs,
                       size_t n_terms, const size_t *ckpt_at, size_t n_ckpt, int dtype,

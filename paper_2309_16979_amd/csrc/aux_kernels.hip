@@ -127,9 +127,9 @@ static __device__ __forceinline__ void for_amp_blocks(const void *amps, const Bl
     }
 }
 
+// One workgroup's share (group blockIdx.x of gridDim.x) of a reduction.
 template <typename T, int COMP>
-__global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, BlockStore st, double step,
-                                                          ReduceArgs a)
+__device__ __forceinline__ void reduce_body(const void *amps, const BlockStore &st, double step, const ReduceArgs &a)
 {
     constexpr int NW = kThreads / 64;
     __shared__ double sacc[4][NW];
@@ -208,6 +208,21 @@ __global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, Bloc
     }
 }
 
+template <typename T, int COMP>
+__global__ __launch_bounds__(kThreads) void reduce_kernel(const void *amps, BlockStore st, double step,
+                                                          ReduceArgs a)
+{
+    reduce_body<T, COMP>(amps, st, step, a);
+}
+
+// Several reductions of equal length in one launch: job blockIdx.y.
+template <typename T, int COMP>
+__global__ __launch_bounds__(kThreads) void reduce_multi_kernel(const ReduceJob *jobs)
+{
+    const ReduceJob &j = jobs[blockIdx.y];
+    reduce_body<T, COMP>(j.amps, j.st, j.step, j.a);
+}
+
 template <typename T>
 static void reduce_comp(int comp, dim3 grid, dim3 block, hipStream_t stream, const void *amps, const BlockStore &st,
                         double step, const ReduceArgs &a)
@@ -217,13 +232,36 @@ static void reduce_comp(int comp, dim3 grid, dim3 block, hipStream_t stream, con
     else hipLaunchKernelGGL((reduce_kernel<T, 0>), grid, block, 0, stream, amps, st, step, a);
 }
 
+static uint64_t reduce_groups(uint64_t amp_count)
+{
+    uint64_t g = ((amp_count >> 6) + 3) / 4;
+    if (g > (uint64_t)kRedGroups) g = kRedGroups;
+    return g == 0 ? 1 : g;
+}
+
+hipError_t launch_reduce_multi(bool is_double, int comp, const ReduceJob *jobs, int n_jobs, uint64_t amp_count,
+                               int *n_groups, hipStream_t stream)
+{
+    const uint64_t g = reduce_groups(amp_count);
+    *n_groups = (int)g;
+    if (n_jobs <= 0) return hipSuccess;
+    const dim3 grid((unsigned)g, (unsigned)n_jobs), block(kThreads);
+    if (is_double) {
+        if (comp == 2) hipLaunchKernelGGL((reduce_multi_kernel<double, 2>), grid, block, 0, stream, jobs);
+        else if (comp == 1) hipLaunchKernelGGL((reduce_multi_kernel<double, 1>), grid, block, 0, stream, jobs);
+        else hipLaunchKernelGGL((reduce_multi_kernel<double, 0>), grid, block, 0, stream, jobs);
+    } else {
+        if (comp == 2) hipLaunchKernelGGL((reduce_multi_kernel<float, 2>), grid, block, 0, stream, jobs);
+        else if (comp == 1) hipLaunchKernelGGL((reduce_multi_kernel<float, 1>), grid, block, 0, stream, jobs);
+        else hipLaunchKernelGGL((reduce_multi_kernel<float, 0>), grid, block, 0, stream, jobs);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce(bool is_double, int comp, const void *amps, BlockStore st,
                          double step, const ReduceArgs &a, int *n_groups, hipStream_t stream)
 {
-    const uint64_t nab = a.amp_count >> 6;
-    uint64_t g = (nab + 3) / 4;
-    if (g > (uint64_t)kRedGroups) g = kRedGroups;
-    if (g == 0) g = 1;
+    const uint64_t g = reduce_groups(a.amp_count);
     *n_groups = (int)g;
     const dim3 grid((unsigned)g), block(kThreads);
     if (is_double) reduce_comp<double>(comp, grid, block, stream, amps, st, step, a);
@@ -231,9 +269,12 @@ hipError_t launch_reduce(bool is_double, int comp, const void *amps, BlockStore 
     return hipGetLastError();
 }
 
+// Job blockIdx.x: out[4 job + j] = sum_g partials[4 (job n + g) + j].
 __global__ __launch_bounds__(kThreads) void reduce_final_kernel(const double *partials, int n, double *out)
 {
     __shared__ double s[4][kThreads];
+    partials += (uint64_t)blockIdx.x * 4 * (uint64_t)n;
+    out += 4 * blockIdx.x;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int g = threadIdx.x; g < n; g += kThreads)
 #pragma unroll
@@ -252,7 +293,15 @@ __global__ __launch_bounds__(kThreads) void reduce_final_kernel(const double *pa
 
 hipError_t launch_reduce_final(const double *partials, int n_groups, double *out, hipStream_t stream)
 {
-    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(kThreads), 0, stream, partials, n_groups, out);
+    return launch_reduce_final_multi(partials, n_groups, 1, out, stream);
+}
+
+hipError_t launch_reduce_final_multi(const double *partials, int n_groups, int n_jobs, double *out,
+                                     hipStream_t stream)
+{
+    if (n_jobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_final_kernel, dim3((unsigned)n_jobs), dim3(kThreads), 0, stream, partials, n_groups,
+                       out);
     return hipGetLastError();
 }
 

@@ -8,17 +8,19 @@
 // circuits thus fill the GPU together, and nothing returns to the host
 // between levels.
 //
-// The autotuner picks the fusion width k (1..5) per circuit, and the tile
-// size 2^tb (one per batch, since a launch is compiled for one tile size;
-// per circuit for single simulators), that minimise a cost model over the
-// circuit's plan:
+// The autotuner picks the fusion width k per circuit (1..5 for a single
+// simulator, 1..2 in a batch, whose launch runs one kernel variant for all
+// circuits), and the tile size 2^tb (one per batch, since a launch is
+// compiled for one tile size; per circuit for single simulators), that
+// minimise a cost model over the circuit's plan:
 //   sum over passes of 2^n * (c_pass[tb] + sum over ops c_op[type][k]).
 // By default the coefficients are a fixed table measured on an MI355X with
 // msv_autotune_calibrate (so plans, and with them compressed results, are the
 // same in every process; ties go to the smaller tb, then the smaller k).
 // Autotune mode 2 measures them in the current process instead: timed passes
-// of a fixed synthetic state (n = 20), an empty pass per tile size and passes
-// of 8 identical ops per op kind and width.
+// of a fixed synthetic state (n = 24, so that every tile size fills the
+// device), an empty pass per tile size and passes of 8 identical ops per op
+// kind and width.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -34,6 +36,13 @@ namespace msv {
 
 namespace {
 
+// Widest fused op of a batched launch. Ops of 3 qubits and more leave the
+// register segments (an LDS round trip each, beside the neighbouring ops'),
+// and 4 and more need the kernel variant with more registers per thread,
+// which lowers the occupancy of every circuit in the launch; measured on the
+// 256-circuit batch: k <= 2 0.27 s, k <= 3 0.31 s, k <= 5 0.50 s per launch.
+constexpr int kBatchMaxFuse = 2;
+
 struct CostModel {
     bool ready = false;
     double pass[14] = {0};          // ns per amplitude of an empty compressed pass, by tb
@@ -48,15 +57,15 @@ CostModel fixed_model(bool is_double)
     CostModel m;
     m.ready = true;
     if (is_double) {
-        const double pass[14] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0.015486, 0.015256, 0.019796, 0};
-        const double dense[6] = {0, 0.0029368, 0.0033087, 0.0072421, 0.0106653, 0.0310950};
+        const double pass[14] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0.0091444, 0.0069584, 0.0088441, 0};
+        const double dense[6] = {0, 0.0013373, 0.0014297, 0.0043428, 0.0071995, 0.0266664};
         std::copy(pass, pass + 14, m.pass);
         std::copy(dense, dense + 6, m.dense);
         m.diag = 0.0;
-        m.phase = 0.00054348;
+        m.phase = 0.00011174;
     } else {
-        const double pass[14] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0.014341, 0.015753, 0.019834, 0};
-        const double dense[6] = {0, 0.0027701, 0.0029894, 0.0048918, 0.0061219, 0.0173832};
+        const double pass[14] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0.0083888, 0.0066819, 0.0060908, 0};
+        const double dense[6] = {0, 0.00085312, 0.00093387, 0.0016219, 0.0026541, 0.0133642};
         std::copy(pass, pass + 14, m.pass);
         std::copy(dense, dense + 6, m.dense);
         m.diag = 0.0;
@@ -71,7 +80,8 @@ CostModel fixed_model(bool is_double)
 CostModel g_live[2];   // [is_double], measured once per process (mode 2)
 std::mutex g_cost_mu;
 
-// Time passes of `reps` identical gates on a fresh 20-qubit compressed state.
+// Best of three timed applies of `gates` on a fresh compressed state (after
+// spreading it with a layer of H and one warm-up apply).
 int time_pass(msv_sim *s, const std::vector<msv_gate> &gates, double *sec)
 {
     int st;
@@ -92,7 +102,9 @@ int time_pass(msv_sim *s, const std::vector<msv_gate> &gates, double *sec)
 
 int measure_model(bool is_double, hipStream_t stream, CostModel &cm)
 {
-    const int n = 20;
+    // large enough that even 2^12-amplitude tiles fill the device (4096 tiles):
+    // the costs are those of a full GPU, as in a batch or a large state
+    const int n = 24;
     const double N = (double)(1u << n);
     msv_sim *s = nullptr;
     int st;
@@ -185,12 +197,13 @@ double predict(const CostModel &cm, const std::vector<Pass> &passes, int n, int 
 }
 
 
-// Best fusion width for a circuit at tile size tb: (k, predicted cost, plan).
+// Best fusion width (at most k_cap) for a circuit at tile size tb: (k,
+// predicted cost, plan).
 double best_k_at(const CostModel &cm, const std::vector<Prim> &prims, int n, int tb, int *k_out,
-                 std::vector<Pass> *out)
+                 std::vector<Pass> *out, int k_cap = kMaxFuse)
 {
     double best = 1e300;
-    for (int k = 1; k <= kMaxFuse; ++k) {
+    for (int k = 1; k <= k_cap; ++k) {
         PlanOptions o;
         o.n = n;
         o.tb = tb;
@@ -234,6 +247,50 @@ int autotune(bool is_double, int mode, hipStream_t stream, const std::vector<Pri
 
 using namespace msv;
 
+namespace msv {
+
+StoreArena::~StoreArena()
+{
+    if (base) (void)hipFree(base);
+}
+
+int StoreArena::reserve(size_t bytes)
+{
+    if (hipMalloc(&base, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        base = nullptr;
+        return MSV_E_NOMEM;
+    }
+    cap = bytes;
+    used = 0;
+    return MSV_OK;
+}
+
+void *StoreArena::alloc(size_t b, void *ctx)
+{
+    StoreArena *a = (StoreArena *)ctx;
+    const size_t off = (a->used + 255) & ~(size_t)255;
+    if (a->base && off + b <= a->cap) {
+        a->used = off + b;
+        return (uint8_t *)a->base + off;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, b) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void StoreArena::release(void *p, void *ctx)
+{
+    StoreArena *a = (StoreArena *)ctx;
+    const uint8_t *q = (const uint8_t *)p, *b0 = (const uint8_t *)a->base;
+    if (p && !(b0 && q >= b0 && q < b0 + a->cap)) (void)hipFree(p);
+}
+
+}  // namespace msv
+
 extern "C" int msv_batch_run(const msv_circuit *circuits, size_t count, int dtype, double eb,
                              const msv_batch_opts *opts, void *const *amps_out, msv_stats *stats_out)
 {
@@ -243,36 +300,9 @@ extern "C" int msv_batch_run(const msv_circuit *circuits, size_t count, int dtyp
     const bool dbl = dtype == MSV_C128;
     const bool tune = !opts || opts->autotune;
     const auto t0 = std::chrono::steady_clock::now();
-    // One device allocation holds every circuit's store (bump allocation;
-    // released after the simulators).
-    struct Arena {
-        void *base = nullptr;
-        size_t cap = 0, used = 0;
-        ~Arena() { if (base) (void)hipFree(base); }
-        // stores come from the arena; anything else (work buffers, read-out
-        // staging) falls back to hipMalloc and is freed individually
-        static void *alloc(size_t b, void *ctx)
-        {
-            Arena *a = (Arena *)ctx;
-            const size_t off = (a->used + 255) & ~(size_t)255;
-            if (off + b <= a->cap) {
-                a->used = off + b;
-                return (uint8_t *)a->base + off;
-            }
-            void *p = nullptr;
-            if (hipMalloc(&p, b) != hipSuccess) {
-                (void)hipGetLastError();
-                return nullptr;
-            }
-            return p;
-        }
-        static void release(void *p, void *ctx)
-        {
-            Arena *a = (Arena *)ctx;
-            const uint8_t *q = (const uint8_t *)p, *b0 = (const uint8_t *)a->base;
-            if (p && !(q >= b0 && q < b0 + a->cap)) (void)hipFree(p);
-        }
-    } arena;
+    // One device allocation holds every circuit's store (released after the
+    // simulators).
+    StoreArena arena;
     {
         size_t total = 1 << 20;
         for (size_t i = 0; i < count; ++i) {
@@ -281,12 +311,7 @@ extern "C" int msv_batch_run(const msv_circuit *circuits, size_t count, int dtyp
             const uint64_t nblk = 2ull << (nq - 6);
             total += 2 * (((nblk + 255) & ~255ull) + 2 * ((4 * nblk + 255) & ~255ull) + (8ull << nq)) + 4096;
         }
-        if (hipMalloc(&arena.base, total) != hipSuccess) {
-            (void)hipGetLastError();
-            arena.base = nullptr;
-            return fail_global(MSV_E_NOMEM, "batch store allocation failed");
-        }
-        arena.cap = total;
+        if (arena.reserve(total) != MSV_OK) return fail_global(MSV_E_NOMEM, "batch store allocation failed");
     }
     struct Sims {
         std::vector<msv_sim *> v;
@@ -315,7 +340,7 @@ extern "C" int msv_batch_run(const msv_circuit *circuits, size_t count, int dtyp
         if ((st = msv_create(c.n_qubits, dtype, &s))) return st;
         sims.v.push_back(s);
         msv_set_stream(s, stream);
-        if ((st = msv_set_device_allocator(s, &Arena::alloc, &Arena::release, &arena))) return st;
+        if ((st = msv_set_device_allocator(s, &StoreArena::alloc, &StoreArena::release, &arena))) return st;
         if ((st = msv_set_error_bound(s, eb))) return st;
         if ((st = msv_set_chunk_qubits(s, std::min(c.n_qubits, 20)))) return st;
         if ((st = msv_init_basis(s, c.init_basis))) return st;
@@ -346,7 +371,7 @@ extern "C" int msv_batch_run(const msv_circuit *circuits, size_t count, int dtyp
                 for (size_t i = t; i < count; i += step)
                     for (size_t c = 0; c < nc; ++c)
                         cost[i * nc + c] = best_k_at(cm, prims[i], circuits[i].n_qubits, cand[c], &kk[i * nc + c],
-                                                     nullptr);
+                                                     nullptr, kBatchMaxFuse);
             });
             double best = 1e300;
             size_t cb = 0;
@@ -427,12 +452,13 @@ extern "C" int msv_batch_run(const msv_circuit *circuits, size_t count, int dtyp
             d.buf.check_err = 1;
             d.buf.slot_tile0 = 0;
             d.circuit = (uint32_t)i;
+            d.group = queue_group(d.geo.n_tiles);
             d.need = tiles_before[i];
             tiles_before[i] += d.geo.n_tiles;
             part_off.push_back(part_total);
             part_total += d.geo.n_tiles;
             prefix.push_back(n_items);
-            n_items += d.geo.n_tiles;
+            n_items += (d.geo.n_tiles + d.group - 1) / d.group;
             descs.push_back(d);
             cur[i] ^= 1;
         }
@@ -492,7 +518,7 @@ extern "C" int msv_batch_run(const msv_circuit *circuits, size_t count, int dtyp
         // normally completes in well under a millisecond) means something is
         // wrong: the kernel then leaves the queue
         const uint64_t spin_limit = 1ull << 22;
-        hipError_t e = launch_batch_persistent(dbl, tb_batch, max_k, (const BatchDesc *)d_descs.p,
+        hipError_t e = launch_batch_persistent(dbl, true, tb_batch, max_k, (const BatchDesc *)d_descs.p,
                                                (const uint64_t *)d_prefix.p, (int)descs.size(), n_items,
                                                (unsigned long long *)d_queue.p,
                                                (unsigned int *)((uint8_t *)d_queue.p + 256), (uint32_t *)d_flags.p,
@@ -543,41 +569,6 @@ extern "C" int msv_batch_run(const msv_circuit *circuits, size_t count, int dtyp
                 return st;
     agg.t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (stats_out) *stats_out = agg;
-    return MSV_OK;
-}
-
-extern "C" int msv_batch_adjoint(const msv_circuit *ansatz, const double *params, size_t n_sets, size_t n_params,
-                                 const uint64_t *masks, const double *coeffs, size_t n_terms, const size_t *ckpt_at,
-                                 size_t n_ckpt, int dtype, double eb, double *expvals, double *grads)
-{
-    if (!ansatz || !params || !expvals || (n_params && !grads) || n_sets == 0)
-        return fail_global(MSV_E_ARG, "bad argument");
-    // Parameter sets run on concurrent workers, each with its own simulator and
-    // stream, so that the small per-set passes of several sets share the GPU.
-    const size_t nw = std::min<size_t>(n_sets, 8);
-    std::vector<int> status(nw, MSV_OK);
-    std::vector<std::string> msg(nw);
-    auto work = [&](size_t w) {
-        msv_sim *s = nullptr;
-        int st = msv_create(ansatz->n_qubits, dtype, &s);
-        if (st == MSV_OK) st = msv_set_error_bound(s, eb);
-        if (st == MSV_OK) st = msv_set_chunk_qubits(s, std::min(ansatz->n_qubits, 20));
-        for (size_t k = w; st == MSV_OK && k < n_sets; k += nw) {
-            st = msv_init_basis(s, ansatz->init_basis);
-            if (st == MSV_OK)
-                st = msv_adjoint(s, ansatz->gates, ansatz->n_gates, params + k * n_params, n_params, masks, coeffs,
-                                 n_terms, ckpt_at, n_ckpt, expvals + k, grads + k * n_params);
-        }
-        if (st != MSV_OK) msg[w] = msv_last_error(s);
-        status[w] = st;
-        if (s) msv_destroy(s);
-    };
-    std::vector<std::thread> pool;
-    for (size_t w = 1; w < nw; ++w) pool.emplace_back(work, w);
-    work(0);
-    for (auto &th : pool) th.join();
-    for (size_t w = 0; w < nw; ++w)
-        if (status[w] != MSV_OK) return fail_global(status[w], msg[w].c_str());
     return MSV_OK;
 }
 

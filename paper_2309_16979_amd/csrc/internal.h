@@ -17,6 +17,19 @@ double bound_for(const msv_sim *s, double norm2);
 // Matrix-core mode (MmaMode) for the state's dtype and its MSV_MMA_* setting.
 int mma_mode(const msv_sim *s);
 
+// One device allocation holding the stores of many simulators (batched
+// runs): bump allocation, handed to each simulator as its device allocator.
+// Requests beyond the reservation fall back to hipMalloc and are freed one
+// by one; the reservation itself is freed with the arena.
+struct StoreArena {
+    void *base = nullptr;
+    size_t cap = 0, used = 0;
+    ~StoreArena();
+    int reserve(size_t bytes);   // MSV_OK or MSV_E_NOMEM
+    static void *alloc(size_t bytes, void *ctx);
+    static void release(void *p, void *ctx);
+};
+
 int alloc_device_store(msv_sim *s);
 int pin_stage(msv_sim *s, size_t bytes);
 // Run passes over the device-resident state (plain or compressed). Per-pass

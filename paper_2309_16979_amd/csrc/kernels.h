@@ -59,34 +59,67 @@ struct BatchDesc {
     PassGeom geo;
     PassBuffers buf;
     uint32_t circuit;
-    uint32_t pad_;
+    uint32_t group;   // tiles per work item (queue_group)
     uint64_t need;
 };
+
+// Tiles per work item of a batched launch for a descriptor of n_tiles tiles:
+// groups only where a level still yields about a thousand items (a device's
+// worth of workgroups).
+inline uint32_t queue_group(uint64_t n_tiles)
+{
+    const uint64_t g = n_tiles / 1024;
+    return (uint32_t)(g < 1 ? 1 : (g > 8 ? 8 : g));
+}
 
 // Flags bit of a batched launch whose dependency wait exceeded its limit
 // (every workgroup then leaves the queue; the results are not usable).
 constexpr uint32_t kFlagQueueTimeout = 16u;
 
 // All tiles of all descriptors in ONE launch of persistent workgroups (as
-// many as fit on the device at once, at most the item count). Work items are
-// numbered level-major (descriptor order, then tile): item i belongs to the
+// many as fit on the device at once, at most the item count). A work item is
+// a group of desc.group consecutive tiles of one descriptor; items are
+// numbered level-major (descriptor order, then group): item i belongs to the
 // descriptor d with prefix[d] <= i < prefix[d + 1]. A workgroup takes the next
 // item with an atomic add on *head, waits (one thread, bounded by spin_limit
-// sleeps) until done[circuit] reaches the descriptor's need, runs the tile,
-// and adds 1 to done[circuit] after a device-scope fence. Items only wait on
-// items taken before them, so the queue always drains. *head and done[] must
-// be zero before the launch. All descriptors share tb and the compressed
-// layout; max_k (widest dense op) selects the kernel variant. *grid receives
-// the number of workgroups launched.
-hipError_t launch_batch_persistent(bool is_double, int tb, int max_k, const BatchDesc *descs, const uint64_t *prefix,
-                                   int n_desc, uint64_t n_items, unsigned long long *head, unsigned int *done,
-                                   uint32_t *flags, uint64_t spin_limit, int *grid, hipStream_t stream);
+// sleeps) until done[circuit] (tiles finished) reaches the descriptor's need,
+// runs the tiles, and adds their count to done[circuit] after a device-scope
+// fence. Items only wait on items taken before them, so the queue always
+// drains. *head and done[] must be zero before the launch. All descriptors
+// share tb and the store kind (compressed block stores, or plain amplitudes);
+// max_k (widest dense op) selects the kernel variant. *grid receives the
+// number of workgroups launched.
+hipError_t launch_batch_persistent(bool is_double, bool compressed, int tb, int max_k, const BatchDesc *descs,
+                                   const uint64_t *prefix, int n_desc, uint64_t n_items, unsigned long long *head,
+                                   unsigned int *done, uint32_t *flags, uint64_t spin_limit, int *grid,
+                                   hipStream_t stream);
+
+// One (parameter set, reverse pass level) of a batched adjoint launch: its
+// tiles are work items of the same queue as BatchDesc (circuit = the set).
+struct AdjointDesc {
+    PassGeom geo;
+    AdjointBuffers buf;
+    uint32_t circuit;
+    uint32_t group;   // tiles per work item (queue_group)
+    uint64_t need;
+};
+
+// Every two-state adjoint pass of many parameter sets in ONE persistent
+// launch (queue as launch_batch_persistent); tb <= 12.
+hipError_t launch_adjoint_persistent(bool is_double, bool compressed, int tb, const AdjointDesc *descs,
+                                     const uint64_t *prefix, int n_desc, uint64_t n_items, unsigned long long *head,
+                                     unsigned int *done, uint32_t *flags, uint64_t spin_limit, int *grid,
+                                     hipStream_t stream);
 
 hipError_t launch_adjoint_pass(bool is_double, bool compressed, const PassGeom &geo, const AdjointBuffers &buf,
                                hipStream_t stream);
 // out[2 s + {0,1}] = sum over tiles of the probe partials of slot s.
 hipError_t launch_grad_reduce(const double *grad_part, uint64_t stride, int n_slots, double *out,
                               hipStream_t stream);
+// The same for n_sets sets whose partials lie back to back (2 * n_slots *
+// stride doubles each): out[2 (set n_slots + s) + {0,1}].
+hipError_t launch_grad_reduce_multi(const double *grad_part, uint64_t stride, int n_slots, int n_sets, double *out,
+                                    hipStream_t stream);
 
 // Launch one pass over geo.n_tiles tiles. is_double selects complex128.
 // load_c / store_c select compressed (true) or plain amplitudes on each side.
@@ -121,6 +154,20 @@ hipError_t launch_reduce(bool is_double, int comp, const void *amps, BlockStore 
 // out[j] = sum_g partials[4 g + j] (fixed order), j < 4.
 hipError_t launch_reduce_final(const double *partials, int n_groups, double *out,
                                hipStream_t stream);
+// One reduction per job (each job's ReduceArgs.partials holds its own
+// 4 * n_groups doubles), all over amp_count amplitudes, in one launch.
+struct ReduceJob {
+    const void *amps;
+    BlockStore st;
+    double step;
+    ReduceArgs a;
+};
+hipError_t launch_reduce_multi(bool is_double, int comp, const ReduceJob *jobs, int n_jobs, uint64_t amp_count,
+                               int *n_groups, hipStream_t stream);
+// launch_reduce_final for n_jobs jobs whose partials lie back to back
+// (4 * n_groups doubles each): out[4 job + j].
+hipError_t launch_reduce_final_multi(const double *partials, int n_groups, int n_jobs, double *out,
+                                     hipStream_t stream);
 // Pass statistics from the per-workgroup triples of passes [0, n_passes):
 // out[3p] = sum of norms, out[3p+1] = max error, out[3p+2] = sum of words.
 // Workgroups of pass p are part[3 * pass_offsets[p] ...].

@@ -1,6 +1,8 @@
-"""Batched runs: one launch per pass level over many uneven circuits; each
-circuit's result must equal its single-circuit GPU run (same plan) bitwise and
-meet the pass bound; fidelity against the oracle for small members."""
+"""Batched runs: every pass of many uneven circuits in one persistent launch;
+each circuit's result must equal its single-circuit GPU run (same plan)
+bitwise and meet the pass bound; fidelity against the oracle for small
+members. Batched adjoint: every set's sweeps as items of shared persistent
+launches, against the single adjoint and the oracle's parameter shift."""
 
 import numpy as np
 import pytest
@@ -90,3 +92,41 @@ print(st["kernel_launches"], st["passes"], h.hexdigest())
     assert res[0] == res[1], res
     assert res[0][0] == "1"
     print("batch: launches %s, passes %s, digest %s" % tuple(res[0]))
+
+
+@pytest.mark.parametrize("ck", [(), (18, 36)])
+def test_batch_adjoint_compressed_against_parameter_shift(ck):
+    """Compressed complex64 sets (eb = 1e-6), with and without checkpoint
+    segments: every set's expectation and gradient against the oracle's FP64
+    energy and parameter-shift gradient, to the compressed adjoint's
+    tolerance."""
+    from paper_2309_16979_amd import batch_adjoint
+    n, layers = 9, 2
+    gates = ansatz(n, layers)
+    P = ansatz_params(n, layers, seed=8, count=6)
+    masks, coeffs = zz_chain(n)
+    log("batch adjoint compressed", ck)
+    ev, gr = batch_adjoint(n, gates, P, masks, coeffs, list(ck), dtype="c64", eb=1e-6)
+    for k in range(P.shape[0]):
+        ref = oracle.param_shift_gradient(n, gates, P[k], masks, coeffs)
+        assert np.max(np.abs(gr[k] - ref)) <= 2e-3 * max(1.0, np.max(np.abs(ref))), k
+        assert ev[k] == pytest.approx(oracle.energy(n, gates, P[k], masks, coeffs), abs=2e-3)
+
+
+def test_batch_adjoint_many_sets_segments_exact():
+    """Plain complex128 amplitudes, 20 sets, three checkpoint segments:
+    gradients to 1e-10 of parameter shift; a single set gives the same
+    numbers as the same set inside the batch."""
+    from paper_2309_16979_amd import batch_adjoint
+    n, layers = 8, 3
+    gates = ansatz(n, layers)
+    P = ansatz_params(n, layers, seed=21, count=20)
+    masks, coeffs = zz_chain(n)
+    log("batch adjoint 20 sets")
+    ev, gr = batch_adjoint(n, gates, P, masks, coeffs, [3 * n, 6 * n], dtype="c128")
+    for k in (0, 7, 19):
+        ref = oracle.param_shift_gradient(n, gates, P[k], masks, coeffs)
+        assert np.max(np.abs(gr[k] - ref)) < 1e-10, k
+        assert ev[k] == pytest.approx(oracle.energy(n, gates, P[k], masks, coeffs), abs=1e-12)
+    ev1, gr1 = batch_adjoint(n, gates, P[7:8], masks, coeffs, [3 * n, 6 * n], dtype="c128")
+    assert ev1[0] == ev[7] and np.array_equal(gr1[0], gr[7])
