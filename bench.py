@@ -71,7 +71,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip comparison runs outside the timed loop")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--workload", default="qft28",
-                    choices=["qft28", "random20", "host34", "adjoint22", "batch256", "table1"])
+                    choices=["qft28", "random20", "host34", "host28", "adjoint22", "batch256", "table1"])
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device copy (scales the HBM byte counters)")
     return ap.parse_args()
@@ -196,11 +196,11 @@ def main():
               "(a state is not sharded across GPUs); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
-    if a.workload == "host34" and not a.torch_runtime:
+    if a.workload in ("host34", "host28") and not a.torch_runtime:
         # the library alone, on the HIP runtime it was built against: no
         # PyTorch in the process (host-store runs need no torch memory)
         os.environ["MSV_TORCH_RUNTIME"] = "0"
-        bench_host34(a)
+        (bench_host34 if a.workload == "host34" else bench_host28)(a)
         return
     import torch
 
@@ -220,7 +220,7 @@ def main():
         print(json.dumps({"copy_probe_bytes": src.numel() * 4}))
         return
     if a.workload != "qft28":
-        {"random20": bench_random20, "host34": bench_host34, "adjoint22": bench_adjoint22,
+        {"random20": bench_random20, "host34": bench_host34, "host28": bench_host28, "adjoint22": bench_adjoint22,
          "batch256": bench_batch256, "table1": bench_table1}[a.workload](a)
         return
     den = None if a.no_probes else probe_denominators()
@@ -432,6 +432,37 @@ def bench_random20(a):
             "print(len(g) * 2.0 ** 20 / (time.perf_counter() - t))" % (ROOT, a.seed))
     r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
     out["oracle_1_thread_updates_per_s"] = float(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 else None
+    print(json.dumps(out), flush=True)
+
+
+def bench_host28(a):
+    """The headline circuit (QFT|x> + 100 random gates, n=28, complex64,
+    eb=1e-5, chunks of 2^20 amplitudes) on the host-pinned store: the same
+    compressed passes, with the chunks streamed from pinned host memory over
+    the host link (the configuration's second store)."""
+    from paper_2309_16979_amd import Simulator
+    from workloads import qft_plus_random
+    use_torch = os.environ.get("MSV_TORCH_RUNTIME", "1") != "0"
+    n, log2c, eb = 28, 20, 1e-5
+    x, gates = qft_plus_random(n, 100, seed=a.seed)
+    with Simulator(n, dtype="c64", eb=eb, chunk_qubits=log2c, store="host", k_max=a.k, use_torch=use_torch) as s:
+        def run():
+            s.init_basis(x)
+            s.apply(gates)
+        run()
+        dt, _ = _timed(run, max(1, a.steps))
+        st = s.stats()
+    link_bytes = st["h2d_bytes"] + st["d2h_bytes"]
+    out = {"metric": "amplitude-gate updates/sec incl. codec and host link", "unit": "amplitude-gate updates/s",
+           "value": len(gates) * float(1 << n) / dt, "n_gpus": 1, "higher_is_better": True, "dtype": "c64",
+           "data": "synthetic: seeded QFT|x> + 100 random gates",
+           "config": {"workload": "qft+100 random, n=28, complex64, chunk 2^20, eb=1e-05, host-pinned store",
+                      "gates": len(gates), "pytorch_in_process": use_torch},
+           "s_per_apply": dt, "passes": st["passes"], "ratio": st["ratio"],
+           "bound_violations": st["bound_violations"],
+           "host_link": {"h2d_bytes": st["h2d_bytes"], "d2h_bytes": st["d2h_bytes"], "overlap": st["overlap"],
+                         "t_kernel": st["t_kernel"], "link_GBps_over_apply": link_bytes / dt / 1e9,
+                         "zero_groups_skipped": st["zero_groups_skipped"]}}
     print(json.dumps(out), flush=True)
 
 

@@ -240,7 +240,10 @@ int msv_init_state(msv_sim *sim, const void *host_amps);
  * undefined and must be re-initialised). */
 int msv_apply(msv_sim *sim, const msv_gate *gates, size_t n_gates);
 
-/* ---- measurement (FP64 reductions on the GPU) ------------------------------ */
+/* ---- measurement (FP64 reductions on the GPU) ------------------------------
+ * The paper defines no read-out calls: these are what a user of a state-vector
+ * simulator reads from the state its passes leave (the stage results of
+ * Sec. 2), each computed from the decoded amplitudes with FP64 sums. */
 
 /* P(qubit = 1) = sum over i with bit q set of |psi_i|^2. */
 int msv_prob_one(msv_sim *sim, int qubit, double *p1);
@@ -375,8 +378,9 @@ typedef struct msv_circuit {
 
 typedef struct msv_batch_opts {
     int32_t autotune;        /* 0 = the k_max and log2_tile below; 1 = choose
-                                the fusion width per circuit and the tile size
-                                of the batch by the fixed cost model (the same
+                                the fusion width per circuit (at most 2) and
+                                the tile size of the batch by the fixed cost
+                                model (the same
                                 plans, hence results, in every process);
                                 2 = the same with the model measured in this
                                 process                                        */
@@ -385,22 +389,23 @@ typedef struct msv_batch_opts {
     int32_t mma_precision;   /* enum msv_mma                                    */
 } msv_batch_opts;
 
-/* Run count circuits (8..30 qubits each, compressed with eb > 0) in ONE
- * launch of persistent workgroups (the batching form of the hot path: many
- * circuits in one persistent launch). Work items are (circuit, pass level,
- * tile) in level-major order on a device queue; a workgroup takes the next
- * item with an atomic add and runs it once its circuit's previous level is
- * complete (per-circuit completion counters, device-scope fences), so small
- * circuits fill the GPU together and nothing returns to the host between
- * levels. All circuits share the tile size (at most 2^min(12, smallest n)).
- * amps_out[i] (host, 2^n_i complex of dtype) may be NULL to skip the copy;
- * stats_out aggregates (kernel_launches = 1). MSV_E_NOMEM when the stores do
- * not fit; MSV_E_DEVICE if a dependency wait ran past its limit. */
+/* Many circuits at once (not a passage of the paper: its stages, Sec. 2,
+ * applied to many states). Run count circuits (8..30 qubits each, compressed
+ * with eb > 0) in ONE launch of persistent workgroups. Work items (groups of
+ * up to 8 tiles of one circuit's pass level) sit in level-major order on a
+ * device queue; a workgroup takes the next item with an atomic add and runs
+ * it once its circuit's previous level is complete (per-circuit tile
+ * counters, device-scope fences), so small circuits fill the GPU together and
+ * nothing returns to the host between levels. All circuits share the tile
+ * size (at most 2^min(12, smallest n)); the fusion width is at most 2 when
+ * autotuned. amps_out[i] (host, 2^n_i complex of dtype) may be NULL to skip
+ * the copy; stats_out aggregates (kernel_launches = 1). MSV_E_NOMEM when the
+ * stores do not fit; MSV_E_DEVICE if a dependency wait ran past its limit. */
 int msv_batch_run(const msv_circuit *circuits, size_t count, int dtype, double eb,
                   const msv_batch_opts *opts, void *const *amps_out,
                   msv_stats *stats_out);
 /* Measure the autotuner's cost model on the current device (complex64 or
- * complex128 states, n = 20, eb = 1e-5): model[0..2] ns per amplitude of a
+ * complex128 states, n = 24, eb = 1e-5): model[0..2] ns per amplitude of a
  * pass with tile sizes 2^10..2^12, model[3..7] of a dense op of width 1..5,
  * model[8] of a diagonal op, model[9] of a controlled phase; cap >= 10. The
  * fixed table of autotune mode 1 came from this call on an MI355X. */

@@ -282,6 +282,7 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
     // iteration when the wave has an even number of them (independent
     // chains for the scheduler; sums keep the one-block order).
     constexpr bool E1_PAIR = NAB % (2 * NW) == 0;
+    double nrm_im = 0.0;   // second FMA chain of the norm (imaginary parts)
     if constexpr (E1_PAIR) for (int jb = wave; jb < NAB; jb += 2 * NW) {
         const int jc = jb + NW;
         const int l0 = swz(jb * 64 + lane), l1 = swz(jc * 64 + lane);
@@ -289,34 +290,52 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
         double d[4];
 #pragma unroll
         for (int p = 0; p < 4; ++p) d[p] = (double)x[p];
-        nrm += d[0] * d[0] + d[1] * d[1];
-        nrm += d[2] * d[2] + d[3] * d[3];
+        nrm = __builtin_fma(d[0], d[0], nrm);
+        nrm_im = __builtin_fma(d[1], d[1], nrm_im);
+        nrm = __builtin_fma(d[2], d[2], nrm);
+        nrm_im = __builtin_fma(d[3], d[3], nrm_im);
+        // codes (quantize, written out so that the check below reuses the
+        // rounded FP64 value: q = r exactly whenever r is in range)
         int32_t q[4];
+        double r[4];
 #pragma unroll
-        for (int p = 0; p < 4; ++p) q[p] = quantize<T>(x[p], inv_step, bad);
+        for (int p = 0; p < 4; ++p) {
+            r[p] = __builtin_rint(d[p] * inv_step);
+            const bool ok = __builtin_fabs(r[p]) <= 1073741823.0;
+            bad |= !ok;
+            q[p] = ok ? (int32_t)r[p] : 0;
+        }
         if (check) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const T yr = dequantize<T>(q[2 * h], step), yi = dequantize<T>(q[2 * h + 1], step);
+                const T yr = (T)(r[2 * h] * step), yi = (T)(r[2 * h + 1] * step);
                 errt = maxT(errt, maxT(absT(x[2 * h] - yr), absT(x[2 * h + 1] - yi)));
             }
         }
         uint32_t u[4], W4[4];
-        int32_t A4[4];
 #pragma unroll
         for (int p = 0; p < 4; ++p) u[p] = residual_zigzag(q[p]);
-        block_width4(u, W4);
+        // widths: when every zigzag of the four blocks fits a byte, one OR
+        // reduction over the four packed side by side gives all four
+        if (__builtin_amdgcn_ballot_w64((u[0] | u[1] | u[2] | u[3]) > 255u) == 0) {
+            const uint32_t o = wave_or(u[0] | (u[1] << 8) | (u[2] << 16) | (u[3] << 24));
 #pragma unroll
-        for (int p = 0; p < 4; ++p) A4[p] = __builtin_amdgcn_readlane(q[p], 0);
+            for (int p = 0; p < 4; ++p) {
+                const uint32_t b = (o >> (8 * p)) & 255u;
+                W4[p] = b ? 32u - (uint32_t)__builtin_clz(b) : 0u;
+            }
+        } else {
+            block_width4(u, W4);
+        }
         reinterpret_cast<uint32_t *>(sre)[l0 * VPT] = u[0];
         reinterpret_cast<uint32_t *>(sim)[l0 * VPT] = u[1];
         reinterpret_cast<uint32_t *>(sre)[l1 * VPT] = u[2];
         reinterpret_cast<uint32_t *>(sim)[l1 * VPT] = u[3];
-        if (lane == 0) {
+        if (lane == 0) {   // lane 0 holds the anchors q_0 itself
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
                 sW[2 * jb + (p & 1) + 2 * NW * (p >> 1)] = W4[p];
-                sA[2 * jb + (p & 1) + 2 * NW * (p >> 1)] = A4[p];
+                sA[2 * jb + (p & 1) + 2 * NW * (p >> 1)] = q[p];
             }
         }
     }
@@ -360,6 +379,7 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
             repredict(ui_p, sW + 2 * jb + 1, sA[2 * jb + 1], lane);
         }
     }
+    nrm += nrm_im;
     err = fmax(err, (double)errt);
     if (bad) atomicOr(flags, 1u);
     __syncthreads();
