@@ -251,6 +251,14 @@ int msv_prob_one(msv_sim *sim, int qubit, double *p1);
  * set bits of m: sum_i |psi_i|^2 sum_k c_k (-1)^popcount(i & m_k). */
 int msv_expect_z(msv_sim *sim, const uint64_t *z_masks, const double *coeffs,
                  size_t n_terms, double *out);
+/* msv_apply followed by msv_expect_z, the same results as the two calls. With
+ * a device-resident store, 1..64 terms and at least one pass, the last pass
+ * takes the expectation over the values it stores (after the encoder's
+ * rounding, as msv_expect_z would decode them), so the state is not read
+ * again; otherwise the two calls run one after the other. Errors as both. */
+int msv_apply_expect_z(msv_sim *sim, const msv_gate *gates, size_t n_gates,
+                       const uint64_t *z_masks, const double *coeffs, size_t n_terms,
+                       double *out);
 /* Copy amplitudes [first, first+count) (decoded) to host_out in the handle's
  * dtype. */
 int msv_get_amplitudes(msv_sim *sim, uint64_t first, uint64_t count, void *host_out);

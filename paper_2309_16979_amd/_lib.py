@@ -59,7 +59,7 @@ EXPORTS = (
     "msv_create", "msv_destroy", "msv_last_error", "msv_set_chunk_qubits", "msv_set_error_bound",
     "msv_set_store", "msv_set_fusion", "msv_set_option", "msv_set_device_allocator",
     "msv_set_stream", "msv_init_basis", "msv_init_state", "msv_apply", "msv_prob_one",
-    "msv_expect_z", "msv_get_amplitudes", "msv_fidelity", "msv_get_stats", "msv_export_chunk",
+    "msv_expect_z", "msv_apply_expect_z", "msv_get_amplitudes", "msv_fidelity", "msv_get_stats", "msv_export_chunk",
     "msv_codec_encode", "msv_codec_encode_mode", "msv_codec_decode", "msv_codec_bound", "msv_adjoint", "msv_batch_run",
     "msv_batch_adjoint", "msv_plan_export", "msv_get_pass_stats", "msv_codec_encode_static",
     "msv_set_error_bound_mode", "msv_qasm_parse", "msv_autotune_calibrate",
@@ -117,6 +117,7 @@ def load():
         "msv_apply": ([P, C.POINTER(Gate), C.c_size_t], C.c_int),
         "msv_prob_one": ([P, C.c_int, C.POINTER(C.c_double)], C.c_int),
         "msv_expect_z": ([P, P, P, C.c_size_t, C.POINTER(C.c_double)], C.c_int),
+        "msv_apply_expect_z": ([P, C.POINTER(Gate), C.c_size_t, P, P, C.c_size_t, C.POINTER(C.c_double)], C.c_int),
         "msv_get_amplitudes": ([P, C.c_uint64, C.c_uint64, P], C.c_int),
         "msv_fidelity": ([P, P, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
         "msv_get_stats": ([P, C.POINTER(Stats)], C.c_int),

@@ -165,7 +165,8 @@ void lower_for(const msv_sim *s, const std::vector<Pass> &passes, const PlanOpti
 }
 
 int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOptions &o, double *norm_last,
-                      double *err_last, double *words_last, std::vector<double> *per_pass, const Lowered *pre)
+                      double *err_last, double *words_last, std::vector<double> *per_pass, const Lowered *pre,
+                      ExpFuse *ex)
 {
     hipStream_t stream = s->stream();
     Lowered own;
@@ -188,10 +189,29 @@ int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOpt
     const size_t ops_bytes = ops.size() * sizeof(OpDesc);
     const size_t offs_bytes = offs.size() * sizeof(uint64_t);
     const size_t a1 = (ops_bytes + 255) & ~(size_t)255, a2 = (pool_bytes + 255) & ~(size_t)255;
+    // the fused expectation needs a last pass without observable ops
+    if (ex) {
+        ex->done = false;
+        bool fuse = n_passes > 0 && ex->n_terms >= 1 && ex->n_terms <= 64;
+        if (fuse)
+            for (int i = geoms[n_passes - 1].op_begin; i < geoms[n_passes - 1].op_begin + geoms[n_passes - 1].n_ops; ++i)
+                fuse = fuse && ops[i].type != OP_OBS;
+        if (!fuse) ex = nullptr;
+    }
+    // staging: ops | pool | offsets | flags word, pass statistics | expectation (32 B) | masks, coefficients
+    const size_t a3 = (a1 + a2 + offs_bytes + 8 + 3 * 8 * n_passes + 63) & ~(size_t)63;
+    const size_t n_ex = ex ? (size_t)ex->n_terms : 0;
     int st;
     // the previous call's copies out of the staging buffer finished at its sync
-    if ((st = pin_stage(s, a1 + a2 + offs_bytes + 3 * 8 * n_passes + 64))) return st;
+    if ((st = pin_stage(s, a3 + 64 + 16 * n_ex))) return st;
     uint8_t *pin = (uint8_t *)s->ws.pin.p;
+    if (ex) {
+        memcpy(pin + a3 + 64, ex->masks, 8 * n_ex);
+        memcpy(pin + a3 + 64 + 8 * n_ex, ex->coeffs, 8 * n_ex);
+        if ((st = dev_alloc(s, s->ws.masks, 16 * n_ex))) return st;
+        if ((st = dev_alloc(s, s->ws.red, std::max<size_t>(4 * 8 * geoms[n_passes - 1].n_tiles, 256)))) return st;
+        if ((st = dev_alloc(s, s->ws.red_out, 256))) return st;
+    }
     if (ops_bytes) memcpy(pin, ops.data(), ops_bytes);
     if (pool_bytes) memcpy(pin + a1, s->is_double() ? (const void *)poold.data() : (const void *)poolf.data(), pool_bytes);
     memcpy(pin + a1 + a2, offs.data(), offs_bytes);
@@ -204,6 +224,7 @@ int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOpt
     if (ops_bytes) HIPCHK(s, hipMemcpyAsync(s->ws.ops.p, pin, ops_bytes, hipMemcpyHostToDevice, stream));
     if (pool_bytes) HIPCHK(s, hipMemcpyAsync(s->ws.pool.p, pin + a1, pool_bytes, hipMemcpyHostToDevice, stream));
     HIPCHK(s, hipMemcpyAsync(s->ws.pass_off.p, pin + a1 + a2, offs_bytes, hipMemcpyHostToDevice, stream));
+    if (ex) HIPCHK(s, hipMemcpyAsync(s->ws.masks.p, pin + a3 + 64, 16 * n_ex, hipMemcpyHostToDevice, stream));
     HIPCHK(s, hipMemsetAsync(s->ws.flags.p, 0, 4, stream));
     double *part = (double *)s->ws.part.p;
     double *pstats = (double *)s->ws.pass_stats.p;
@@ -235,6 +256,12 @@ int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOpt
         b.in_pred = s->in_pred();
         b.ops = (const OpDesc *)s->ws.ops.p;
         b.pool = s->ws.pool.p;
+        if (ex && p + 1 == n_passes) {
+            b.obs_masks = (const uint64_t *)s->ws.masks.p;
+            b.obs_coeffs = (const double *)((uint8_t *)s->ws.masks.p + 8 * n_ex);
+            b.obs_terms = ex->n_terms;
+            b.exp_part = (double *)s->ws.red.p;
+        }
         const bool c = s->compressed();
         if (c && s->pred_mode) s->pred_used = true;
         if (s->time_passes) HIPCHK(s, hipEventRecord(ev[2 * p], stream));
@@ -250,11 +277,22 @@ int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOpt
         HIPCHK(s, launch_pass_stats(part, (const uint64_t *)s->ws.pass_off.p, (int)n_passes, pstats, stream));
     double *hout = (double *)(pin + a1 + a2 + offs_bytes + 8);
     uint32_t *hflags = (uint32_t *)(pin + a1 + a2 + offs_bytes);
+    double *hexp = (double *)(pin + a3);
+    if (ex) {
+        HIPCHK(s, launch_reduce_final((const double *)s->ws.red.p, (int)geoms[n_passes - 1].n_tiles,
+                                      (double *)s->ws.red_out.p, stream));
+        HIPCHK(s, hipMemcpyAsync(hexp, s->ws.red_out.p, 32, hipMemcpyDeviceToHost, stream));
+        ++s->stats.kernel_launches;
+    }
     if (n_passes)
         HIPCHK(s, hipMemcpyAsync(hout, pstats, 3 * 8 * n_passes, hipMemcpyDeviceToHost, stream));
     HIPCHK(s, hipMemcpyAsync(hflags, s->ws.flags.p, 4, hipMemcpyDeviceToHost, stream));
     HIPCHK(s, hipStreamSynchronize(stream));
     if (per_pass) per_pass->assign(hout, hout + 3 * n_passes);
+    if (ex) {
+        ex->value = hexp[1];
+        ex->done = true;
+    }
     s->pass_log.assign(hout, hout + 3 * n_passes);
     s->stats.t_pass = 0.0;
     for (size_t p = 0; p < ev.size() / 2; ++p) {
@@ -641,10 +679,11 @@ int msv_init_state(msv_sim *s, const void *host)
     return MSV_OK;
 }
 
-int msv_apply(msv_sim *s, const msv_gate *gates, size_t n_gates)
+// msv_apply; with ex, the last pass also takes the expectation ex asks for
+// (device-resident stores only; ex->done tells whether it did).
+static int apply_gates(msv_sim *s, const msv_gate *gates, size_t n_gates, ExpFuse *ex)
 {
-    GUARD(s);
-    if (!s->inited) return fail(s, MSV_E_STATE, "state not initialised");
+    if (ex) ex->done = false;
     if (n_gates && !gates) return fail(s, MSV_E_ARG, "null gate list");
     std::vector<Prim> prims(n_gates);
     std::string err;
@@ -723,7 +762,7 @@ int msv_apply(msv_sim *s, const msv_gate *gates, size_t n_gates)
         HIPCHK(s, hipEventCreate(&e0));
         HIPCHK(s, hipEventCreate(&e1));
         HIPCHK(s, hipEventRecord(e0, s->stream()));
-        st = run_passes_device(s, passes, o, &norm, &err_last, &words, nullptr, &s->plan_low);
+        st = run_passes_device(s, passes, o, &norm, &err_last, &words, nullptr, &s->plan_low, ex);
         if (st == MSV_OK) {
             HIPCHK(s, hipEventRecord(e1, s->stream()));
             HIPCHK(s, hipEventSynchronize(e1));
@@ -746,6 +785,27 @@ int msv_apply(msv_sim *s, const msv_gate *gates, size_t n_gates)
     s->stats.gates = n_gates;
     s->stats.t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return st;
+}
+
+int msv_apply(msv_sim *s, const msv_gate *gates, size_t n_gates)
+{
+    GUARD(s);
+    if (!s->inited) return fail(s, MSV_E_STATE, "state not initialised");
+    return apply_gates(s, gates, n_gates, nullptr);
+}
+
+int msv_apply_expect_z(msv_sim *s, const msv_gate *gates, size_t n_gates, const uint64_t *masks,
+                       const double *coeffs, size_t n_terms, double *out)
+{
+    GUARD(s);
+    if (!s->inited) return fail(s, MSV_E_STATE, "state not initialised");
+    if (!out || (n_terms && (!masks || !coeffs)) || n_terms > 4096) return fail(s, MSV_E_ARG, "bad terms");
+    ExpFuse ex{masks, coeffs, (int)n_terms, 0.0, false};
+    int st = apply_gates(s, gates, n_gates, n_terms <= 64 ? &ex : nullptr);
+    if (st) return st;
+    if (!ex.done) return msv_expect_z(s, masks, coeffs, n_terms, out);
+    *out = ex.value * s->scale * s->scale;
+    return MSV_OK;
 }
 
 // Reduction over the whole state; out4 = {sum |psi|^2, q1, q2, q3}.

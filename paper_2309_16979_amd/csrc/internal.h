@@ -34,9 +34,20 @@ int alloc_device_store(msv_sim *s);
 int pin_stage(msv_sim *s, size_t bytes);
 // Run passes over the device-resident state (plain or compressed). Per-pass
 // (norm, max error, words) triples go to per_pass when given.
+// A Z-string expectation taken by the last pass of run_passes_device over
+// the values it stores (device-resident stores, 1..64 terms): sum_t
+// coeffs[t] <Z(masks[t])> without the pending scale. done is set when the
+// passes took it.
+struct ExpFuse {
+    const uint64_t *masks;
+    const double *coeffs;
+    int n_terms;
+    double value;
+    bool done;
+};
 int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOptions &o, double *norm_last,
                       double *err_last, double *words_last, std::vector<double> *per_pass,
-                      const Lowered *pre = nullptr);
+                      const Lowered *pre = nullptr, ExpFuse *ex = nullptr);
 // Lower passes for the state's real type.
 void lower_for(const msv_sim *s, const std::vector<Pass> &passes, const PlanOptions &o, Lowered &low);
 

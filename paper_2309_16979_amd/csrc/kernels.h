@@ -36,9 +36,11 @@ struct PassBuffers {
     int32_t in_pred;             // compressed input may carry predictors other than 0
     const OpDesc *ops;
     const void *pool;            // matrix pool, complex of the state's real type
-    const uint64_t *obs_masks;   // OP_OBS: Z masks and coefficients
+    const uint64_t *obs_masks;   // OP_OBS (and exp_part): Z masks and coefficients
     const double *obs_coeffs;
     int32_t obs_terms;
+    double *exp_part;            // if set (obs_terms <= 64): per workgroup 4 doubles, [1] = its
+                                 // share of sum_t c_t <Z(m_t)> over the stored (decoded) values
 };
 
 // Two states of one adjoint pass: psi and lambda = U^dagger ... O psi. Each

@@ -36,7 +36,7 @@ __device__ __forceinline__ void pass_tile(const PassGeom &geo, const PassBuffers
     __shared__ uint32_t sW[NSB];
     __shared__ int32_t sA[NSB];
     __shared__ uint32_t sOff[NSB];
-    __shared__ double sred[2 * NW];
+    __shared__ double sred[3 * NW];
     // phase-op tables during the ops; per wave, 128 words of plane-word
     // staging during the decode and payload offsets during the encode
     constexpr int SX = (PhaseScratch<TB>::size * (int)sizeof(T) + 7) / 8 > 128 * NW
@@ -83,6 +83,12 @@ __device__ __forceinline__ void pass_tile(const PassGeom &geo, const PassBuffers
         __syncthreads();
     }
 
+    // the expectation of the stored state, when the caller asks for it with
+    // this (last) pass; the store below overwrites the tile's values
+    double ex = 0.0;
+    if (buf.exp_part)
+        ex = wave_sum_f64(tile_expect<T, TB, STOREC>(sre, sim, sG, buf.obs_masks, buf.obs_coeffs, buf.obs_terms,
+                                                       buf.inv_step, buf.step, wave, lane));
     double nrm = 0.0, err = 0.0;
     const uint64_t slot = (tile - buf.slot_tile0) * (uint64_t)(32 * NSB);
     static_assert(NSB <= 256, "per-wave offsets hold 256 words");
@@ -93,7 +99,7 @@ __device__ __forceinline__ void pass_tile(const PassGeom &geo, const PassBuffers
     // per-workgroup statistics (fixed reduction order)
     nrm = wave_sum_f64(nrm);
     err = wave_max_f64(err);
-    if (lane == 0) { sred[wave] = nrm; sred[NW + wave] = err; }
+    if (lane == 0) { sred[wave] = nrm; sred[NW + wave] = err; sred[2 * NW + wave] = ex; }
     __syncthreads();
     if (tid == 0 && buf.part) {
         double a = 0.0, e = 0.0;
@@ -102,6 +108,15 @@ __device__ __forceinline__ void pass_tile(const PassGeom &geo, const PassBuffers
         buf.part[3 * pidx] = a;
         buf.part[3 * pidx + 1] = e;
         buf.part[3 * pidx + 2] = (double)words;
+    }
+    if (tid == 0 && buf.exp_part) {
+        double x = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) x += sred[2 * NW + w];
+        buf.exp_part[4 * pidx] = 0.0;
+        buf.exp_part[4 * pidx + 1] = x;
+        buf.exp_part[4 * pidx + 2] = 0.0;
+        buf.exp_part[4 * pidx + 3] = 0.0;
     }
 }
 

@@ -206,6 +206,53 @@ __device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, co
     }
 }
 
+// ----------------------------------------------------------- expectation
+
+// This thread's share of sum_t c_t <psi| Z(m_t) |psi> (t < n_terms <= 64)
+// over the tile, taken on the values the store will hold: the decoder's
+// values (T)(q * 2 eb) when storing compressed, the amplitudes themselves
+// otherwise. Per 64-amplitude block G (lane = index bits 0..5) the sum is
+// sum_t c_t (-1)^popcount(G & h_t) P^(l_t) with l_t / h_t the low 6 / high
+// bits of m_t and P^ the Walsh-Hadamard transform of the block's
+// probabilities over the lanes, the same form as the reduction kernel.
+template <typename T, int TB, bool STOREC>
+__device__ __forceinline__ double tile_expect(const T *sre, const T *sim, const uint64_t *sG, const uint64_t *masks,
+                                              const double *coeffs, int n_terms, double inv_step, double step,
+                                              int wave, int lane)
+{
+    constexpr int NAB = 1 << (TB - 6), NW = kThreads / 64;
+    double ct = 0.0;
+    uint64_t mhi = 0;
+    int lsrc = 0;
+    if (lane < n_terms) {
+        ct = coeffs[lane];
+        mhi = masks[lane] >> 6;
+        lsrc = (int)(masks[lane] & 63u);
+    }
+    const double s0 = (lane & 1) ? -1.0 : 1.0, s1 = (lane & 2) ? -1.0 : 1.0, s2 = (lane & 4) ? -1.0 : 1.0,
+                 s3 = (lane & 8) ? -1.0 : 1.0, s4 = (lane & 16) ? -1.0 : 1.0, s5 = (lane & 32) ? -1.0 : 1.0;
+    double acc = 0.0;
+    for (int jb = wave; jb < NAB; jb += NW) {
+        const int l = swz(jb * 64 + lane);
+        double xr = (double)sre[l], xi = (double)sim[l];
+        if (STOREC) {
+            const double rr = __builtin_rint(xr * inv_step), ri = __builtin_rint(xi * inv_step);
+            xr = __builtin_fabs(rr) <= 1073741823.0 ? (double)(T)(rr * step) : 0.0;
+            xi = __builtin_fabs(ri) <= 1073741823.0 ? (double)(T)(ri * step) : 0.0;
+        }
+        double P = xr * xr + xi * xi;
+        P = __builtin_fma(s0, P, __shfl_xor(P, 1, 64));
+        P = __builtin_fma(s1, P, __shfl_xor(P, 2, 64));
+        P = __builtin_fma(s2, P, __shfl_xor(P, 4, 64));
+        P = __builtin_fma(s3, P, __shfl_xor(P, 8, 64));
+        P = __builtin_fma(s4, P, __shfl_xor(P, 16, 64));
+        P = __builtin_fma(s5, P, __shfl_xor(P, 32, 64));
+        const double ph = __shfl(P, lsrc, 64);
+        acc += ((__popcll(sG[jb] & mhi) & 1) ? -ct : ct) * ph;
+    }
+    return acc;
+}
+
 // ----------------------------------------------------------------- store
 
 // Predictor mode 1 for one block held as Lorenzo-1 zigzags (*u_p, this

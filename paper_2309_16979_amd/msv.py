@@ -182,6 +182,18 @@ class Simulator:
         self._chk(self._L.msv_expect_z(self.h, m.ctypes.data, c.ctypes.data, len(m), C.byref(out)))
         return out.value
 
+    def apply_expect_z(self, gates: Sequence, masks: Iterable[int], coeffs: Iterable[float]) -> float:
+        """apply(gates) then expect_z(masks, coeffs); the last pass takes the
+        expectation when the store is device-resident and there are 1..64 terms."""
+        arr, keep = gate_array(gates)
+        m = np.ascontiguousarray(list(masks), dtype=np.uint64)
+        c = np.ascontiguousarray(list(coeffs), dtype=np.float64)
+        out = C.c_double()
+        self._chk(self._L.msv_apply_expect_z(self.h, arr, len(gates), m.ctypes.data, c.ctypes.data, len(m),
+                                             C.byref(out)))
+        del keep
+        return out.value
+
     def amplitudes(self, first: int = 0, count: Optional[int] = None) -> np.ndarray:
         if count is None:
             count = (1 << self.n) - first
