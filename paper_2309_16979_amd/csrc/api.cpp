@@ -322,7 +322,7 @@ int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOpt
             for (int i = geoms[p].op_begin; i < geoms[p].op_begin + geoms[p].n_ops; ++i) {
                 const OpDesc &d = ops[i];
                 if (d.type == OP_DENSE) gate += amps * (d.real ? 2.0 : 4.0) * (double)(1 << d.k);
-                else if (d.type == OP_DIAG) gate += amps * 4.0;
+                else if (d.type == OP_DIAG || d.type == OP_RDIAG) gate += amps * 4.0;
                 else if (d.type == OP_PHASE || d.type == OP_RPHASE) gate += amps * 8.0;
                 else if (d.type == OP_MFMA) mflops += amps * 8.0 * (double)(1 << d.k);
             }

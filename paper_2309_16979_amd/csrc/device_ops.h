@@ -21,6 +21,10 @@ enum OpType : int32_t {
     OP_SEG = 7,     // start of a register segment: the next k ops run on per-thread
                     // registers; pos[0..TB-8) = register tile bits (ascending),
                     // ctrl_local = their mask
+    OP_RDIAG = 8,   // diagonal inside a register segment: table bits reordered as
+                    // [register bits (ascending rank) | thread bits | fixed bits];
+                    // slot = register bits, diag = thread bits, pos / gq in that
+                    // order, ctrl_local = mask of the register ranks used
 };
 
 // Matrix-core mode of a pass launch.

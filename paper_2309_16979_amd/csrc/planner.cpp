@@ -600,6 +600,39 @@ bool lower_passes(const std::vector<Pass> &passes, const PlanOptions &o, std::ve
                 for (const cd &v : h.m) push(v);
             } else if (h.type == OP_OBS) {
                 d.k = 0;
+            } else if (h.type == OP_DIAG && sid >= 0) {
+                // diagonal on registers: the table is reordered so that a
+                // thread's entries for its register elements are one contiguous
+                // row, selected by its thread bits and the tile's fixed bits
+                d.type = OP_RDIAG;
+                d.k = (int32_t)h.q.size();
+                ok = ok && d.k >= 1 && d.k <= 5 && (int)h.m.size() == (1 << d.k);
+                const uint32_t S = seg_mask[sid];
+                std::vector<int> rb, tb_, ub;   // table bits m by kind
+                for (int m = 0; m < d.k; ++m) {
+                    const int p = tpos(h.q[m]);
+                    (p >= 0 && ((S >> p) & 1u) ? rb : p >= 0 ? tb_ : ub).push_back(m);
+                }
+                std::sort(rb.begin(), rb.end(), [&](int a, int b) { return tpos(h.q[a]) < tpos(h.q[b]); });
+                std::vector<int> order(rb);
+                order.insert(order.end(), tb_.begin(), tb_.end());
+                order.insert(order.end(), ub.begin(), ub.end());
+                d.slot = (int32_t)rb.size();
+                d.diag = (int32_t)tb_.size();
+                d.ctrl_local = 0;
+                for (int j = 0; j < d.k; ++j) {
+                    d.gq[j] = h.q[order[j]];
+                    d.pos[j] = tpos(h.q[order[j]]);
+                }
+                for (int m : rb) {
+                    const int p = tpos(h.q[m]);
+                    d.ctrl_local |= 1u << __builtin_popcount(S & ((1u << p) - 1u));
+                }
+                for (int v = 0; v < (1 << d.k); ++v) {
+                    int s = 0;
+                    for (int j = 0; j < d.k; ++j) s |= ((v >> j) & 1) << order[j];
+                    push(h.m[s]);
+                }
             } else if (h.type == OP_DIAG) {
                 d.k = (int32_t)h.q.size();
                 ok = ok && d.k >= 1 && d.k <= 5 && (int)h.m.size() == (1 << d.k);

@@ -197,6 +197,72 @@ __device__ __forceinline__ void reg_diag(T *re, T *im, const OpDesc &op, uint32_
     }
 }
 
+// Diagonal with the table reordered by the planner (OP_RDIAG): the thread's
+// 2^popcount(RM) entries form one row, entry v for the register elements whose
+// register bits in RM (ascending) spell v. The row is uniform when the op has
+// no thread bits (scalar loads), else per thread. Same arithmetic as reg_diag.
+__host__ __device__ constexpr int extract_bits(int i, int m)
+{
+    int r = 0, j = 0;
+    for (int b = 0; b < 8; ++b)
+        if ((m >> b) & 1) r |= ((i >> b) & 1) << j++;
+    return r;
+}
+
+template <typename T, int R, int RM, bool UNIFORM>
+__device__ __forceinline__ void reg_rdiag_apply(T *re, T *im, const T *__restrict__ row)
+{
+    constexpr int NV = 1 << __builtin_popcount(RM);
+    T dr[NV], di[NV];
+    if (UNIFORM) {
+        const ConstPtr<T> rc = as_const(row);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) { dr[v] = rc[2 * v]; di[v] = rc[2 * v + 1]; }
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) { dr[v] = row[2 * v]; di[v] = row[2 * v + 1]; }
+    }
+#pragma unroll
+    for (int i = 0; i < (1 << R); ++i) {
+        const int v = extract_bits(i, RM);
+        const T xr = re[i], xi = im[i];
+        re[i] = fmaT(xr, dr[v], -xi * di[v]);
+        im[i] = fmaT(xr, di[v], xi * dr[v]);
+    }
+    variant_end<3000 + RM + (UNIFORM ? 100 : 0)>();
+}
+
+template <typename T, int R, bool UNIFORM, int RM = 0>
+__device__ __forceinline__ void reg_rdiag_at(int rm, T *re, T *im, const T *row)
+{
+    if constexpr (RM < (1 << R)) {
+        if (rm == RM) reg_rdiag_apply<T, R, RM, UNIFORM>(re, im, row);
+        else reg_rdiag_at<T, R, UNIFORM, RM + 1>(rm, re, im, row);
+    }
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void reg_rdiag(T *re, T *im, const OpDesc &op, int tbase, const T *__restrict__ dv,
+                                          uint64_t base)
+{
+    // (loops over every descriptor field with constant indices: a run-time
+    // index into the descriptor would move it to scratch memory)
+    const int br = op.slot, bt = op.diag;
+    int u = 0;   // the tile's fixed bits (uniform)
+#pragma unroll
+    for (int j = 0; j < 5; ++j)
+        if (j >= br + bt && j < op.k) u |= (int)((base >> op.gq[j]) & 1ull) << (j - br - bt);
+    if (bt == 0) {
+        reg_rdiag_at<T, R, true>((int)op.ctrl_local, re, im, dv + 2 * (u << br));
+    } else {
+        int t = u << bt;
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+            if (j >= br && j < br + bt) t |= ((tbase >> op.pos[j]) & 1) << (j - br);
+        reg_rdiag_at<T, R, false>((int)op.ctrl_local, re, im, dv + 2 * (t << br));
+    }
+}
+
 // ------------------------------------------------------ controlled phase
 
 // RC: register bit of the control (0 <= RC < R, so every element knows its
@@ -214,7 +280,7 @@ __device__ __forceinline__ void reg_phase_apply(T *re, T *im, T f0r, T f0i, T f1
         for (int i = 0; i < NR; ++i) {
             const T u0r = U0[2 * i], u0i = U0[2 * i + 1], u1r = U1[2 * i], u1i = U1[2 * i + 1];
             const T ur = on_t ? u1r : u0r, ui = on_t ? u1i : u0i;
-            const T pr = fr * ur - fi * ui, pi = fr * ui + fi * ur;
+            const T pr = fmaT(fr, ur, -(fi * ui)), pi = fmaT(fr, ui, fi * ur);
             const T xr = re[i], xi = im[i];
             re[i] = fmaT(xr, pr, -xi * pi);
             im[i] = fmaT(xr, pi, xi * pr);
@@ -225,7 +291,7 @@ __device__ __forceinline__ void reg_phase_apply(T *re, T *im, T f0r, T f0i, T f1
             const bool on = ((i >> RC) & 1) != 0;
             const T fr = on ? f1r : f0r, fi = on ? f1i : f0i;
             const T ur = on ? U1[2 * i] : U0[2 * i], ui = on ? U1[2 * i + 1] : U0[2 * i + 1];
-            const T pr = fr * ur - fi * ui, pi = fr * ui + fi * ur;
+            const T pr = fmaT(fr, ur, -(fi * ui)), pi = fmaT(fr, ui, fi * ur);
             const T xr = re[i], xi = im[i];
             re[i] = fmaT(xr, pr, -xi * pi);
             im[i] = fmaT(xr, pi, xi * pr);
@@ -312,6 +378,8 @@ __device__ __forceinline__ void run_segment(T *samp, const OpDesc &seg, const Op
         const T *M = pool + 2 * (int64_t)op.mat;
         if (op.type == OP_DENSE) {
             if (op.ctrl_fixed == 0 || (base & op.ctrl_fixed) == op.ctrl_fixed) reg_dense<T, R>(re, im, op, smask, M);
+        } else if (op.type == OP_RDIAG) {
+            reg_rdiag<T, R>(re, im, op, tbase, M, base);
         } else if (op.type == OP_DIAG) {
             reg_diag<T, R>(re, im, op, smask, tbase, M, base);
         } else if (op.type == OP_RPHASE) {
