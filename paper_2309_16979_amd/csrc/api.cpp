@@ -209,7 +209,8 @@ int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOpt
         memcpy(pin + a3 + 64, ex->masks, 8 * n_ex);
         memcpy(pin + a3 + 64 + 8 * n_ex, ex->coeffs, 8 * n_ex);
         if ((st = dev_alloc(s, s->ws.masks, 16 * n_ex))) return st;
-        if ((st = dev_alloc(s, s->ws.red, std::max<size_t>(4 * 8 * geoms[n_passes - 1].n_tiles, 256)))) return st;
+        if ((st = dev_alloc(s, s->ws.red, std::max<size_t>(4 * 8 * (geoms[n_passes - 1].n_tiles + 64), 256))))
+            return st;
         if ((st = dev_alloc(s, s->ws.red_out, 256))) return st;
     }
     if (ops_bytes) memcpy(pin, ops.data(), ops_bytes);
@@ -279,8 +280,17 @@ int run_passes_device(msv_sim *s, const std::vector<Pass> &passes, const PlanOpt
     uint32_t *hflags = (uint32_t *)(pin + a1 + a2 + offs_bytes);
     double *hexp = (double *)(pin + a3);
     if (ex) {
-        HIPCHK(s, launch_reduce_final((const double *)s->ws.red.p, (int)geoms[n_passes - 1].n_tiles,
-                                      (double *)s->ws.red_out.p, stream));
+        // per-workgroup partials: in 64 groups first when there are many
+        const double *ep = (const double *)s->ws.red.p;
+        const uint64_t nt = geoms[n_passes - 1].n_tiles;
+        if (nt >= 4096 && nt % 64 == 0) {
+            double *mid = (double *)s->ws.red.p + 4 * nt;
+            HIPCHK(s, launch_reduce_final_multi(ep, (int)(nt / 64), 64, mid, stream));
+            ep = mid;
+            ++s->stats.kernel_launches;
+        }
+        HIPCHK(s, launch_reduce_final(ep, ep == (const double *)s->ws.red.p ? (int)nt : 64, (double *)s->ws.red_out.p,
+                                      stream));
         HIPCHK(s, hipMemcpyAsync(hexp, s->ws.red_out.p, 32, hipMemcpyDeviceToHost, stream));
         ++s->stats.kernel_launches;
     }
