@@ -129,7 +129,8 @@ __device__ __forceinline__ void adjoint_tile(const PassGeom &geo, const AdjointB
 template <typename T, int TB, bool COMP, bool PRED>
 __global__ __launch_bounds__(kThreads) void adjoint_kernel(PassGeom geo, AdjointBuffers buf)
 {
-    adjoint_tile<T, TB, COMP, PRED>(geo, buf, geo.tile_begin + blockIdx.x, blockIdx.x);
+    const uint32_t b = xcd_tile();
+    adjoint_tile<T, TB, COMP, PRED>(geo, buf, geo.tile_begin + b, b);
 }
 
 // Every two-state pass of many parameter sets: (set, level, tile) items of

@@ -130,13 +130,7 @@ template <int TB, int KMAX> struct PassOccupancy { static constexpr int waves = 
 template <typename T, int TB, bool LOADC, bool STOREC, int KMAX, int MF, bool PRED>
 __global__ __launch_bounds__(kThreads, (PassOccupancy<TB, KMAX>::waves)) void pass_kernel(PassGeom geo, PassBuffers buf)
 {
-    // Workgroups go to the 8 XCDs in turn (workgroup b to XCD b mod 8), each
-    // with its own L2. Tile b' = (b mod 8) (n / 8) + b / 8 gives every XCD one
-    // contiguous eighth of the tiles, so neighbouring tiles, whose block
-    // records and payloads share cache lines, meet in the same L2.
-    const uint32_t nb = gridDim.x;
-    uint32_t b = blockIdx.x;
-    if ((nb & 7u) == 0) b = (b & 7u) * (nb >> 3) + (b >> 3);
+    const uint32_t b = xcd_tile();
     pass_tile<T, TB, LOADC, STOREC, KMAX, MF, PRED>(geo, buf, geo.tile_begin + b, b);
 }
 

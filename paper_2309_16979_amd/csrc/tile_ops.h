@@ -57,6 +57,16 @@ __device__ __forceinline__ OpDesc load_op(const OpDesc *p)
     return o;
 }
 
+// Workgroups go to the 8 XCDs in turn (workgroup b to XCD b mod 8), each
+// with its own L2. Tile b' = (b mod 8) (n / 8) + b / 8 of a grid of n gives
+// every XCD one contiguous eighth of the tiles, so neighbouring tiles, whose
+// block records and payloads share cache lines, meet in the same L2.
+__device__ __forceinline__ uint32_t xcd_tile()
+{
+    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    return (nb & 7u) == 0 ? (b & 7u) * (nb >> 3) + (b >> 3) : b;
+}
+
 // ------------------------------------------------------------- geometry
 
 // LDS position of tile element l within its plane: bits 6.. are XOR-folded
