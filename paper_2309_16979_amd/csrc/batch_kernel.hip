@@ -17,7 +17,7 @@ __global__ __launch_bounds__(kThreads, (PassOccupancy<TB, KMAX>::waves)) void ba
     unsigned long long *head, unsigned int *done, uint32_t *flags, uint64_t spin_limit)
 {
     run_queue(descs, prefix, n_desc, n_items, head, done, flags, spin_limit, [&](const BatchDesc &d, uint64_t local) {
-        pass_tile<T, TB, COMP, COMP, KMAX, MMA_NONE, false>(d.geo, d.buf, d.geo.tile_begin + local, local);
+        pass_tile<T, TB, COMP, COMP, KMAX, MMA_NONE, false, false>(d.geo, d.buf, d.geo.tile_begin + local, local);
     });
 }
 

@@ -252,6 +252,37 @@ __device__ __forceinline__ void block_width4(const uint32_t *u_in, uint32_t *w)
     }
 }
 
+// One step of a 32 x 32 bit transpose within each half-wave: lanes l and
+// l ^ J exchange the bit groups the other one needs. The lower lane keeps its
+// bits at positions with bit J clear (mask M) and takes the upper lane's bits
+// there, shifted up by J, into the others; the upper lane keeps its bits at
+// positions with bit J set and takes the lower lane's, shifted down by J.
+// Branch-free: both shifts are one rotate by a per-lane amount, and one bit
+// select merges.
+template <int J, uint32_t M>
+__device__ __forceinline__ uint32_t transpose_step(uint32_t x, uint32_t lane)
+{
+    const uint32_t p = (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, (J << 10) | 0x1f);   // lane ^ J
+    const uint32_t up = 0u - ((lane / J) & 1u);                                     // all ones on the upper lane
+    const uint32_t keep = M ^ up;                                                   // M, or ~M on the upper lane
+    const uint32_t rot = (32u - J) + (up & (uint32_t)(2 * J - 32));                 // 32 - J, or J on the upper lane
+    const uint32_t sh = __builtin_amdgcn_alignbit(p, p, rot);                       // p rotated right by rot
+    return (x & keep) | (sh & ~keep);
+}
+
+// Transpose of the 32 x 32 bit matrix held by each half-wave (row = lane,
+// column = bit): afterwards bit i of lane 32h + j is bit j of the input of
+// lane 32h + i.
+__device__ __forceinline__ uint32_t transpose32_halves(uint32_t x, uint32_t lane)
+{
+    x = transpose_step<16, 0x0000ffffu>(x, lane);
+    x = transpose_step<8, 0x00ff00ffu>(x, lane);
+    x = transpose_step<4, 0x0f0f0f0fu>(x, lane);
+    x = transpose_step<2, 0x33333333u>(x, lane);
+    x = transpose_step<1, 0x55555555u>(x, lane);
+    return x;
+}
+
 // Codes of four blocks (two amplitude blocks, both planes each) from their
 // width bytes Wb, unpacked in one loop up to the largest width. The words are
 // staged in LDS: stage[32 p + k] holds word k of block p (0 at or beyond its
@@ -260,7 +291,9 @@ __device__ __forceinline__ void block_width4(const uint32_t *u_in, uint32_t *w)
 // unpack_codes2. Blocks of predictor 0 only (every block of mode 0) take one
 // scan; other predictors take a second scan (Lorenzo-2) or none (none).
 // PRED = false: the blocks are known to use predictor 0.
-template <bool PRED = true>
+// XP = false keeps the plane-by-plane unpack for every width (fewer live
+// registers, for kernels that are short of them).
+template <bool PRED = true, bool XP = true>
 __device__ __forceinline__ void unpack_codes4_lds(const uint64_t *stage, const uint32_t *Wb, const int32_t *A,
                                                   int32_t *q)
 {
@@ -273,11 +306,23 @@ __device__ __forceinline__ void unpack_codes4_lds(const uint64_t *stage, const u
     }
     const uint32_t Wm = max(max(W[0], W[1]), max(W[2], W[3]));
     uint32_t u[4] = {0u, 0u, 0u, 0u};
-    for (uint32_t k = Wm; k-- > 0;) {
+    if (XP && Wm <= 8u) {
+        // every zigzag fits a byte: lane 8p + k of each half-wave takes its
+        // half of block p's plane k (staged words beyond a block's width are
+        // zero), and the half-wave transpose hands every lane its four values
+        // as u0 | u1 << 8 | u2 << 16 | u3 << 24
+        const uint32_t lane = lane_id(), j = lane & 31u;
+        const uint32_t y = reinterpret_cast<const uint32_t *>(stage)[2u * (32u * (j >> 3) + (j & 7u)) + (lane >> 5)];
+        const uint32_t x = transpose32_halves(y, lane);
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const uint64_t t = stage[32 * p + k] << up;
-            u[p] = __builtin_amdgcn_alignbit(u[p], (uint32_t)(t >> 32), 31u);
+        for (int p = 0; p < 4; ++p) u[p] = (x >> (8 * p)) & 255u;
+    } else {
+        for (uint32_t k = Wm; k-- > 0;) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const uint64_t t = stage[32 * p + k] << up;
+                u[p] = __builtin_amdgcn_alignbit(u[p], (uint32_t)(t >> 32), 31u);
+            }
         }
     }
     if (!PRED || (P[0] | P[1] | P[2] | P[3]) == 0) {
@@ -314,6 +359,28 @@ __device__ __forceinline__ void pack_planes4(const uint32_t *u, const uint32_t *
             if (lane == k) mine[p] = bal;
         }
     }
+}
+
+// Bit planes of four blocks whose zigzags all fit a byte (widths w0..w3 <= 8),
+// written to heap[o_p + k] for k < w_p: the same words as pack_planes4. The
+// four values of a lane travel as one word u0 | u1 << 8 | u2 << 16 | u3 << 24;
+// after the half-wave transposes, lane 8p + k of the low half holds the low 32
+// bits of block p's plane k and the same lane of the high half its high 32
+// bits. Widths and offsets (< 2^16 words within a tile) are picked per lane
+// from packed words (shifts, not an indexed array, which would go to scratch).
+__device__ __forceinline__ void store_planes4_bytes(const uint32_t *u, uint32_t w0, uint32_t w1, uint32_t w2,
+                                                    uint32_t w3, uint32_t o0, uint32_t o1, uint32_t o2, uint32_t o3,
+                                                    uint64_t *heap, uint32_t lane)
+{
+    uint32_t x = u[0] | (u[1] << 8) | (u[2] << 16) | (u[3] << 24);
+    x = transpose32_halves(x, lane);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)x, 32, 64);
+    const uint32_t wp = w0 | (w1 << 8) | (w2 << 16) | (w3 << 24);
+    const uint32_t w = (wp >> (lane & 24u)) & 255u;                          // block (lane >> 3) & 3
+    const uint32_t oa = (lane & 16u) ? (o2 | (o3 << 16)) : (o0 | (o1 << 16));
+    const uint32_t off = (oa >> ((lane & 8u) << 1)) & 0xffffu;
+    const uint32_t k = lane & 7u;
+    if (lane < 32 && k < w) heap[off + k] = (uint64_t)x | ((uint64_t)hi << 32);
 }
 
 // Predictor mode 1 for two blocks: given the codes q, their Lorenzo-1

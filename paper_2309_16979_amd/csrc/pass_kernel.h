@@ -22,7 +22,9 @@ namespace msv {
 // One tile of a pass: decode -> ops -> encode, then the workgroup's FP64
 // statistics into part[3 pidx ..]. Shared by the single-state pass kernel and
 // the batched kernel.
-template <typename T, int TB, bool LOADC, bool STOREC, int KMAX, int MF, bool PRED>
+// XP: the codec's half-wave bit transposes (off in the persistent batch
+// kernel, whose queue state leaves fewer registers for them).
+template <typename T, int TB, bool LOADC, bool STOREC, int KMAX, int MF, bool PRED, bool XP = true>
 __device__ __forceinline__ void pass_tile(const PassGeom &geo, const PassBuffers &buf, uint64_t tile, uint64_t pidx)
 {
     constexpr int TILE = 1 << TB;
@@ -52,7 +54,7 @@ __device__ __forceinline__ void pass_tile(const PassGeom &geo, const PassBuffers
     __syncthreads();
 
     const double sc = buf.scale_src ? 1.0 / __builtin_sqrt(*buf.scale_src) : buf.scale;
-    tile_load<T, TB, LOADC, PRED>(sre, sim, sG, buf.amps_in, buf.in, buf.step, sc, wave, lane, sx + 128 * wave);
+    tile_load<T, TB, LOADC, PRED, XP>(sre, sim, sG, buf.amps_in, buf.in, buf.step, sc, wave, lane, sx + 128 * wave);
     __syncthreads();
 
     const T *pool = (const T *)buf.pool;
@@ -92,7 +94,7 @@ __device__ __forceinline__ void pass_tile(const PassGeom &geo, const PassBuffers
     double nrm = 0.0, err = 0.0;
     const uint64_t slot = (tile - buf.slot_tile0) * (uint64_t)(32 * NSB);
     static_assert(NSB <= 256, "per-wave offsets hold 256 words");
-    const uint32_t words = tile_store<T, TB, STOREC, true, PRED>(sre, sim, sG, sW, sA, sOff, buf.amps_out, buf.out, slot,
+    const uint32_t words = tile_store<T, TB, STOREC, true, PRED, XP>(sre, sim, sG, sW, sA, sOff, buf.amps_out, buf.out, slot,
                                                            buf.inv_step, buf.step, buf.check_err, buf.pred_mode, buf.flags, nrm,
                                                            err, wave, lane,
                                                            reinterpret_cast<uint32_t *>(sx + 128 * wave));

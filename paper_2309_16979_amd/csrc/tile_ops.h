@@ -109,7 +109,7 @@ __device__ __forceinline__ void tile_blocks(const PassGeom &geo, uint64_t base, 
 // stage: 128 words of LDS for this wave, through which the compressed decode
 // broadcasts plane words (unpack_codes4_lds). PRED = false: every block of
 // the input uses predictor 0.
-template <typename T, int TB, bool LOADC, bool PRED = true>
+template <typename T, int TB, bool LOADC, bool PRED = true, bool XP = true>
 __device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, const void *amps, const BlockStore &in,
                                           double step, double sc, int wave, int lane, uint64_t *stage)
 {
@@ -184,7 +184,7 @@ __device__ __forceinline__ void tile_load(T *sre, T *sim, const uint64_t *sG, co
 #pragma unroll
                     for (int p = 0; p < 4; ++p) stage[32 * p + lane] = mine[2 * a + p];
                 }
-                unpack_codes4_lds<PRED>(stage, W4, A4, q4);
+                unpack_codes4_lds<PRED, XP>(stage, W4, A4, q4);
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     T xr = dequantize<T>(q4[2 * h], step), xi = dequantize<T>(q4[2 * h + 1], step);
@@ -304,7 +304,9 @@ __device__ __forceinline__ void repredict(uint32_t *u_p, uint32_t *w_p, int32_t 
 // OWN_OFF: `own_off` (2^(TB-5) words of LDS for this wave) receives the
 // payload offsets: every wave scans the widths itself (E2), so E3 needs no
 // second barrier. Otherwise wave 0 scans into sOff.
-template <typename T, int TB, bool STOREC, bool OWN_OFF = false, bool PRED = true>
+// XP: bit planes of four blocks whose widths are all <= 8 by one half-wave
+// transpose (store_planes4_bytes); false keeps one ballot per plane and block.
+template <typename T, int TB, bool STOREC, bool OWN_OFF = false, bool PRED = true, bool XP = true>
 __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *sG, uint32_t *sW, int32_t *sA,
                                                uint32_t *sOff, void *amps, const BlockStore &out, uint64_t slot,
                                                double inv_step, double step, int check, int pred_mode,
@@ -473,12 +475,17 @@ __device__ __forceinline__ uint32_t tile_store(T *sre, T *sim, const uint64_t *s
                                    reinterpret_cast<const uint32_t *>(sim)[l1 * VPT]};
             constexpr uint32_t WM = PRED ? 0xffu : ~0u;   // without PRED sW holds the width alone
             const uint32_t W4[4] = {sW[2 * jb] & WM, sW[2 * jb + 1] & WM, sW[2 * jc] & WM, sW[2 * jc + 1] & WM};
-            uint64_t m[4];
-            pack_planes4(u, W4, m);
             const uint32_t o4[4] = {so[2 * jb], so[2 * jb + 1], so[2 * jc], so[2 * jc + 1]};
+            if (XP && max(max(W4[0], W4[1]), max(W4[2], W4[3])) <= 8u) {
+                store_planes4_bytes(u, W4[0], W4[1], W4[2], W4[3], o4[0], o4[1], o4[2], o4[3], out.heap + slot,
+                                    (uint32_t)lane);
+            } else {
+                uint64_t m[4];
+                pack_planes4(u, W4, m);
 #pragma unroll
-            for (int p = 0; p < 4; ++p)
-                if ((uint32_t)lane < W4[p]) out.heap[slot + o4[p] + lane] = m[p];
+                for (int p = 0; p < 4; ++p)
+                    if ((uint32_t)lane < W4[p]) out.heap[slot + o4[p] + lane] = m[p];
+            }
         }
     } else {
         for (int jb = wave; jb < NAB; jb += NW) {
