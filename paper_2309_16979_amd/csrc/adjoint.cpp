@@ -624,17 +624,22 @@ extern "C" int msv_batch_adjoint(const msv_circuit *ansatz, const double *params
     const size_t per_set = (S + (comp ? 4 : 2)) * store_bytes + 4096;
     if (arena.reserve(per_set * n_sets + (1 << 20)) != MSV_OK)
         return fail_global(MSV_E_NOMEM, "batched adjoint store allocation failed");
+    // the sets share the stream: one wait for it, then each simulator is
+    // destroyed without its own
     struct Sims {
+        hipStream_t stream;
         std::vector<msv_sim *> v;
         std::vector<std::vector<DevMem>> extra;
         ~Sims()
         {
+            (void)hipStreamSynchronize(stream);
             for (size_t i = 0; i < v.size(); ++i) {
                 for (auto &m : extra[i]) dev_free(v[i], m);
+                v[i]->stream_drained = true;
                 msv_destroy(v[i]);
             }
         }
-    } sims;
+    } sims{stream, {}, {}};
     // slot ids per set: 0 .. S-1 checkpoints, then A, B, L0, L1
     const int A = (int)S, B = (int)S + 1, L0 = (int)S + 2, L1 = (int)S + 3;
     std::vector<std::vector<Slot>> slots(n_sets, std::vector<Slot>(S + 4));

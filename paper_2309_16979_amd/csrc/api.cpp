@@ -405,7 +405,7 @@ void msv_destroy(msv_sim *s)
 {
     if (!s) return;
     hipStream_t st = s->stream();
-    if (st && !s->poisoned) (void)hipStreamSynchronize(st);
+    if (st && !s->poisoned && !s->stream_drained) (void)hipStreamSynchronize(st);
     dev_free(s, s->amps);
     dev_free(s, s->lam_amps);
     for (auto &d : s->lam) {
@@ -565,13 +565,16 @@ int msv_set_stream(msv_sim *s, void *hip_stream)
 {
     GUARD(s);
     s->user_stream = (hipStream_t)hip_stream;
-    return MSV_OK;
+    // without a caller's stream the handle works on one of its own
+    return hip_stream ? MSV_OK : ensure_stream(s);
 }
 
 static int prepare_state_memory(msv_sim *s)
 {
     int st;
-    if ((st = ensure_stream(s))) return st;
+    // a handle on a caller's stream creates none of its own (a batch of
+    // hundreds of handles would pay a stream creation and destruction each)
+    if (!s->user_stream && (st = ensure_stream(s))) return st;
     if (s->store == MSV_STORE_HOST_PINNED) {
         if (!s->compressed()) return fail(s, MSV_E_ARG, "the host store holds compressed chunks: set eb > 0");
         return MSV_OK;

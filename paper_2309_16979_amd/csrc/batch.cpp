@@ -313,14 +313,24 @@ extern "C" int msv_batch_run(const msv_circuit *circuits, size_t count, int dtyp
         }
         if (arena.reserve(total) != MSV_OK) return fail_global(MSV_E_NOMEM, "batch store allocation failed");
     }
-    struct Sims {
-        std::vector<msv_sim *> v;
-        ~Sims() { for (auto *s : v) msv_destroy(s); }
-    } sims;
     hipStream_t stream = nullptr;
     if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess)
         return fail_global(MSV_E_DEVICE, "stream creation failed");
     struct SG { hipStream_t s; ~SG() { (void)hipStreamDestroy(s); } } sg{stream};
+    // the simulators share the batch's stream: one wait for it, then each is
+    // destroyed without its own (declared after sg, so destroyed before it)
+    struct Sims {
+        hipStream_t stream;
+        std::vector<msv_sim *> v;
+        ~Sims()
+        {
+            (void)hipStreamSynchronize(stream);
+            for (auto *s : v) {
+                s->stream_drained = true;
+                msv_destroy(s);
+            }
+        }
+    } sims{stream, {}};
     // per circuit: simulator state, plan
     std::vector<std::vector<Pass>> plans(count);
     std::vector<std::vector<Prim>> prims(count);

@@ -130,6 +130,7 @@ struct msv_sim {
     uint64_t compressed_words = 0;  // payload words of the current state
 
     hipStream_t stream() const { return user_stream ? user_stream : own_stream; }
+    bool stream_drained = false;   // set by an owner that has waited for the stream: destroy skips its wait
     bool is_double() const { return dtype == MSV_C128; }
     size_t elt() const { return dtype == MSV_C128 ? 16 : 8; }
     bool compressed() const { return eb > 0.0; }
