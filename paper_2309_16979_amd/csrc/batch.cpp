@@ -417,20 +417,36 @@ extern "C" int msv_batch_run(const msv_circuit *circuits, size_t count, int dtyp
     std::vector<std::vector<PassGeom>> geoms(count);
     std::vector<size_t> pool_off(count);
     size_t max_levels = 0, fused = 0, total_gates = 0;
+    // each circuit lowered on its own (in parallel), then appended in order
+    std::vector<std::vector<OpDesc>> lops(count);
+    std::vector<std::vector<float>> lpf(count);
+    std::vector<std::vector<double>> lpd(count);
+    std::vector<char> lok(count, 0);
+    {
+        const unsigned nt = std::max(1u, std::min<unsigned>(16, std::thread::hardware_concurrency()));
+        auto lower_some = [&](unsigned t) {
+            for (size_t i = t; i < count; i += nt) {
+                PlanOptions o;
+                o.n = circuits[i].n_qubits;
+                o.tb = tbs[i];
+                o.k_max = ks[i];
+                o.segments = true;
+                lok[i] = dbl ? lower_passes<double>(plans[i], o, lops[i], lpd[i], geoms[i])
+                             : lower_passes<float>(plans[i], o, lops[i], lpf[i], geoms[i]);
+            }
+        };
+        std::vector<std::thread> pool;
+        for (unsigned t = 1; t < nt; ++t) pool.emplace_back(lower_some, t);
+        lower_some(0);
+        for (auto &th : pool) th.join();
+    }
     for (size_t i = 0; i < count; ++i) {
-        PlanOptions o;
-        o.n = circuits[i].n_qubits;
-        o.tb = tbs[i];
-        o.k_max = ks[i];
-        o.segments = true;
         const size_t op0 = ops.size();
         pool_off[i] = dbl ? pd.size() / 2 : pf.size() / 2;
-        std::vector<OpDesc> oi;
-        std::vector<float> pfi;
-        std::vector<double> pdi;
-        const bool ok = dbl ? lower_passes<double>(plans[i], o, oi, pdi, geoms[i])
-                            : lower_passes<float>(plans[i], o, oi, pfi, geoms[i]);
-        if (!ok) return fail_global(MSV_E_ARG, "internal planner error (batch)");
+        std::vector<OpDesc> &oi = lops[i];
+        const std::vector<float> &pfi = lpf[i];
+        const std::vector<double> &pdi = lpd[i];
+        if (!lok[i]) return fail_global(MSV_E_ARG, "internal planner error (batch)");
         for (OpDesc &d : oi) d.mat += (int32_t)pool_off[i];
         for (auto &g : geoms[i]) g.op_begin += (int32_t)op0;
         ops.insert(ops.end(), oi.begin(), oi.end());
