@@ -179,3 +179,32 @@ def test_expectation_many_terms(dtype, eb, n_terms):
         e = p * (eb * (1 + 2.0 ** -20) + 2.0 ** -23) * math.sqrt(2.0 * (1 << n)) + len(gates) * 1e-6
         tol = csum * (2 * e + e * e)
     assert got == pytest.approx(ref, abs=tol)
+
+
+@pytest.mark.parametrize("eb", [0.0, 1e-6])
+def test_stream_handover(eb):
+    """A handle on the caller's (torch's) stream creates no stream of its own;
+    when the caller withdraws its stream (msv_set_stream(NULL)) the handle
+    continues on one of its own. Both halves of the circuit against the
+    oracle, the second half applied after the handover."""
+    n = 14
+    gates = random_circuit(n, 12, seed=31)
+    h = len(gates) // 2
+    psi = oracle.simulate(n, gates, 5)
+    log("stream handover", eb)
+    with _sim(n, "c128", eb=eb, chunk_qubits=12) as s:
+        s.init_basis(5)
+        s.apply(gates[:h])
+        s._chk(s._L.msv_set_stream(s.h, None))
+        s.apply(gates[h:])
+        got = s.amplitudes()
+        st = s.stats()
+    if eb == 0.0:
+        assert max_abs(got, psi) < 1e-12
+    else:
+        # each pass adds an error of 2-norm <= eb' sqrt(2 * 2^n); the unitary
+        # passes after it keep its norm (st counts the second apply's passes,
+        # so the first half's are bounded by the circuit's gate count)
+        assert st["bound_violations"] == 0
+        e = (st["passes"] + h) * st["err_bound"] * math.sqrt(2.0 * (1 << n))
+        assert np.linalg.norm(np.asarray(got, np.complex128) - psi) < e + 1e-12
