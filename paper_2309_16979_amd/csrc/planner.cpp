@@ -153,6 +153,16 @@ struct Fuser {
     std::vector<int> Q;
     std::vector<cd> M;
     std::vector<Prim> diags;          // pending diagonal prims
+    // The pending run's qubits, and its controlled-linear-phase form built up
+    // one prim at a time (phase_ok false once a prim does not fit it), so
+    // that testing one more prim costs O(1) instead of a pass over the run.
+    uint64_t diag_mask = 0;
+    struct PhaseAcc {
+        HostOp op;
+        int pend_a = -1, pend_b = -1;
+        double pend_g = 0.0;
+    } acc;
+    bool phase_ok = false;
 
     Fuser(const PlanOptions &opt, const std::vector<int> &loc) : o(opt), local(loc) {}
 
@@ -177,51 +187,105 @@ struct Fuser {
         return U.size() <= 5;
     }
 
-    bool phase_form(const std::vector<Prim> &ds, HostOp &op) const
+    void phase_start(PhaseAcc &a) const
     {
-        op = HostOp();
-        op.type = OP_PHASE;
-        op.mu.assign(o.n, 0.0);
-        op.lam.assign(o.n, 0.0);
-        int pend_a = -1, pend_b = -1;
-        double pend_g = 0.0;
-        for (const Prim &p : ds) {
-            if (p.q.size() == 1) {
-                op.global *= p.m[0];
-                op.mu[p.q[0]] += std::arg(p.m[1] / p.m[0]);
-                continue;
-            }
-            const int a = p.q[0], b = p.q[1];
-            const cd d0 = p.m[0], d1 = p.m[1], d2 = p.m[2], d3 = p.m[3];
-            op.global *= d0;
-            op.mu[a] += std::arg(d1 / d0);
-            op.mu[b] += std::arg(d2 / d0);
-            const double gam = std::arg(d3 * d0 / (d1 * d2));
-            if (gam == 0.0) continue;
-            if (op.hub < 0 && pend_a < 0) { pend_a = a; pend_b = b; pend_g = gam; continue; }
-            if (op.hub < 0) {
-                if (a == pend_a || a == pend_b) op.hub = a;
-                else if (b == pend_a || b == pend_b) op.hub = b;
-                else return false;
-                op.lam[op.hub == pend_a ? pend_b : pend_a] += pend_g;
-            }
-            if (a == op.hub) op.lam[b] += gam;
-            else if (b == op.hub) op.lam[a] += gam;
+        a = PhaseAcc();
+        a.op.type = OP_PHASE;
+        a.op.mu.assign(o.n, 0.0);
+        a.op.lam.assign(o.n, 0.0);
+    }
+
+    // One more diagonal prim in the controlled-linear-phase form; false when
+    // it does not fit (a's contents are then undefined).
+    static bool phase_add(PhaseAcc &a, const Prim &p)
+    {
+        HostOp &op = a.op;
+        if (p.q.size() == 1) {
+            op.global *= p.m[0];
+            op.mu[p.q[0]] += std::arg(p.m[1] / p.m[0]);
+            return true;
+        }
+        const int x = p.q[0], y = p.q[1];
+        const cd d0 = p.m[0], d1 = p.m[1], d2 = p.m[2], d3 = p.m[3];
+        op.global *= d0;
+        op.mu[x] += std::arg(d1 / d0);
+        op.mu[y] += std::arg(d2 / d0);
+        const double gam = std::arg(d3 * d0 / (d1 * d2));
+        if (gam == 0.0) return true;
+        if (op.hub < 0 && a.pend_a < 0) {
+            a.pend_a = x;
+            a.pend_b = y;
+            a.pend_g = gam;
+            return true;
+        }
+        if (op.hub < 0) {
+            if (x == a.pend_a || x == a.pend_b) op.hub = x;
+            else if (y == a.pend_a || y == a.pend_b) op.hub = y;
             else return false;
+            op.lam[op.hub == a.pend_a ? a.pend_b : a.pend_a] += a.pend_g;
         }
-        if (op.hub < 0 && pend_a >= 0) {
-            op.hub = pend_b;
-            op.lam[pend_a] += pend_g;
-        }
+        if (x == op.hub) op.lam[y] += gam;
+        else if (y == op.hub) op.lam[x] += gam;
+        else return false;
         return true;
     }
 
-    bool diag_fits(const std::vector<Prim> &ds) const
+    // The finished form: a lone pending pair takes its second qubit as hub.
+    static void phase_finish(PhaseAcc &a)
     {
-        std::vector<int> U;
-        if (diag_union(ds, U)) return true;
-        HostOp op;
-        return phase_form(ds, op);
+        if (a.op.hub < 0 && a.pend_a >= 0) {
+            a.op.hub = a.pend_b;
+            a.op.lam[a.pend_a] += a.pend_g;
+        }
+    }
+
+    bool phase_form(const std::vector<Prim> &ds, HostOp &op) const
+    {
+        PhaseAcc a;
+        phase_start(a);
+        for (const Prim &p : ds)
+            if (!phase_add(a, p)) return false;
+        phase_finish(a);
+        op = a.op;
+        return true;
+    }
+
+    static uint64_t mask_of(const Prim &p)
+    {
+        uint64_t m = 0;
+        for (int q : p.q) m |= 1ull << q;
+        return m;
+    }
+
+    // Start a run of diagonal prims with p.
+    void diags_begin(const Prim &p)
+    {
+        diags.clear();
+        diags.push_back(p);
+        diag_mask = mask_of(p);
+        phase_start(acc);
+        phase_ok = phase_add(acc, p);
+        open = DIAGS;
+    }
+
+    // Add p to the pending run if the extended run still fits a table over
+    // <= 5 qubits or the controlled-linear-phase form (the test on the
+    // whole extended run, without a pass over it).
+    bool diags_try(const Prim &p)
+    {
+        const uint64_t m = diag_mask | mask_of(p);
+        bool ph = false;
+        PhaseAcc next;
+        if (phase_ok) {
+            next = acc;
+            ph = phase_add(next, p);
+        }
+        if (__builtin_popcountll(m) > 5 && !ph) return false;
+        diags.push_back(p);
+        diag_mask = m;
+        phase_ok = ph;
+        if (ph) acc = std::move(next);
+        return true;
     }
 
     void flush_diags()
@@ -282,15 +346,12 @@ struct Fuser {
                 return;
             }
             if (open == DIAGS) {
-                diags.push_back(p);
-                if (diag_fits(diags)) return;
-                diags.pop_back();
+                if (diags_try(p)) return;
                 flush_diags();
             } else {
                 flush();
             }
-            diags.push_back(p);
-            open = DIAGS;
+            diags_begin(p);
             return;
         }
         std::vector<int> qs = p.q;
