@@ -163,44 +163,7 @@ __device__ __forceinline__ void reg_dense(T *re, T *im, const OpDesc &op, uint32
 
 // ------------------------------------------------------------- diagonal
 
-// Table bit m comes from register bit rank(pos[m]) (pos[m] in S), from the
-// thread's tile bits, or from the tile's base (pos[m] < 0).
-template <typename T, int R>
-__device__ __forceinline__ void reg_diag(T *re, T *im, const OpDesc &op, uint32_t smask, int tbase,
-                                         const T *__restrict__ dv, uint64_t base)
-{
-    int s_t = 0, rb[5];
-#pragma unroll
-    for (int m = 0; m < 5; ++m) {
-        rb[m] = -1;
-        if (m >= op.k) continue;
-        const int p = op.pos[m];
-        if (p < 0) s_t |= (int)((base >> op.gq[m]) & 1ull) << m;
-        else if ((smask >> p) & 1u) rb[m] = reg_rank(smask, p);
-        else s_t |= ((tbase >> p) & 1) << m;
-    }
-    T dr[1 << R], di[1 << R];
-#pragma unroll
-    for (int i = 0; i < (1 << R); ++i) {
-        int s = s_t;
-#pragma unroll
-        for (int m = 0; m < 5; ++m)
-            if (rb[m] >= 0) s |= ((i >> rb[m]) & 1) << m;
-        dr[i] = dv[2 * s];
-        di[i] = dv[2 * s + 1];
-    }
-#pragma unroll
-    for (int i = 0; i < (1 << R); ++i) {
-        const T xr = re[i], xi = im[i];
-        re[i] = fmaT(xr, dr[i], -xi * di[i]);
-        im[i] = fmaT(xr, di[i], xi * dr[i]);
-    }
-}
-
-// Diagonal with the table reordered by the planner (OP_RDIAG): the thread's
-// 2^popcount(RM) entries form one row, entry v for the register elements whose
-// register bits in RM (ascending) spell v. The row is uniform when the op has
-// no thread bits (scalar loads), else per thread. Same arithmetic as reg_diag.
+// The bits of i at the set positions of m, packed from bit 0 up.
 __host__ __device__ constexpr int extract_bits(int i, int m)
 {
     int r = 0, j = 0;
@@ -209,6 +172,11 @@ __host__ __device__ constexpr int extract_bits(int i, int m)
     return r;
 }
 
+// Diagonal with the table reordered by the planner (OP_RDIAG): the thread's
+// 2^popcount(RM) entries form one row, entry v for the register elements whose
+// register bits in RM (ascending) spell v. The row is uniform when the op has
+// no thread bits (scalar loads), else per thread. The products keep the FMA
+// order of op_diag, so a diagonal gives the same bits in both paths.
 template <typename T, int R, int RM, bool UNIFORM>
 __device__ __forceinline__ void reg_rdiag_apply(T *re, T *im, const T *__restrict__ row)
 {
@@ -380,8 +348,6 @@ __device__ __forceinline__ void run_segment(T *samp, const OpDesc &seg, const Op
             if (op.ctrl_fixed == 0 || (base & op.ctrl_fixed) == op.ctrl_fixed) reg_dense<T, R>(re, im, op, smask, M);
         } else if (op.type == OP_RDIAG) {
             reg_rdiag<T, R>(re, im, op, tbase, M, base);
-        } else if (op.type == OP_DIAG) {
-            reg_diag<T, R>(re, im, op, smask, tbase, M, base);
         } else if (op.type == OP_RPHASE) {
             reg_phase<T, R>(re, im, op, smask, tbase, M, base, tile);
         }
